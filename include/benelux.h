@@ -1,0 +1,159 @@
+/*
+ * benelux.h -- C-ABI of the MI355X (gfx950) Benelux-pair search library.
+ *
+ * What it computes (Hercher, "On one of Erdos' Problems -- An Efficient Search
+ * for Benelux Pairs", arXiv:2506.01099):
+ *   rad(n)      product of the distinct primes dividing n, rad(1) = 1
+ *               (Section 2.1, definition of the radical; computed by the sieve
+ *               of Algorithm 1).
+ *   S_x         the set {rad(x), rad(x+1)} (Section 2.1, before Algorithm 2).
+ *   pair (m,n)  m < n with S_m = S_n.  First kind: rad(m) = rad(n) and
+ *               rad(m+1) = rad(n+1); second kind: rad(m) = rad(n+1) and
+ *               rad(m+1) = rad(n) (Section 1).  A collision is of the first kind
+ *               when rad(m) = rad(n), else of the second (Algorithm 2).
+ *               Every pair inside a group of equal sets is reported, as the
+ *               probe chains of Algorithm 3 do.
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: BX_OK (0) on success, a negative BX_E* code on failure; the
+ *     message of the last failure on the calling thread is bx_last_error().
+ *   - Integers are unsigned 64-bit.  Every value whose radical is needed must be
+ *     below BX_VALUE_LIMIT (2^42) and at most the context's hi_max.
+ *   - Pair lists are malloc'd by the library, sorted by (query, m, n), and
+ *     released by the caller with bx_free().  An empty result is count 0 and a
+ *     NULL list.
+ *   - Calls on one context are serialised by the library (one at a time); use
+ *     one context per host thread for concurrency.
+ *   - All device work runs on the context's HIP stream (bx_set_stream); every
+ *     blocking call returns after that stream has drained.
+ */
+#ifndef BENELUX_H
+#define BENELUX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BX_VALUE_LIMIT (1ull << 42)
+
+enum { BX_FIRST = 1, BX_SECOND = 2, BX_BOTH = 3 };
+
+enum {
+  BX_OK = 0,
+  BX_EINVAL = -1,    /* bad argument: lo = 0, hi < lo, kinds not in {1,2,3}, NULL pointer */
+  BX_ERANGE = -2,    /* a value needs a radical beyond hi_max or BX_VALUE_LIMIT         */
+  BX_ENOMEM = -3,    /* host or device allocation failed, or the HBM budget is too small */
+  BX_EDEVICE = -4,   /* a HIP runtime error; the message names it                       */
+  BX_EBUSY = -5,     /* serving: admission refused (budget or slots) with wait = 0      */
+  BX_EINTERNAL = -6  /* a device-side consistency check failed (see bx_last_error)     */
+};
+
+/* One reported pair.  kind is 1 or 2; query is the index of the range query it
+ * belongs to (0 for single-range calls). */
+typedef struct {
+  uint64_t m;
+  uint64_t n;
+  uint32_t kind;
+  uint32_t query;
+} bx_pair;
+
+typedef struct bx_ctx bx_ctx;
+
+/* Create a context on HIP device `device` able to sieve values up to hi_max
+ * (< 2^42).  It builds the prime tables (all primes <= sqrt(hi_max), and every
+ * odd prime power p^k <= hi_max with k >= 2; the "list of primes sent to the
+ * GPU once" of Section 3.1) and keeps them resident in device memory.
+ * hbm_budget_bytes bounds the device workspace (0 = 85% of free memory).
+ * Errors: BX_EINVAL (NULL ctx), BX_ERANGE (hi_max too large), BX_EDEVICE,
+ * BX_ENOMEM. */
+int bx_create(bx_ctx** ctx, int device, uint64_t hi_max, uint64_t hbm_budget_bytes);
+void bx_destroy(bx_ctx* ctx);
+
+/* Use `hip_stream` (a hipStream_t, e.g. torch's current stream) for all later
+ * device work of this context; NULL restores the context's own stream.  The
+ * caller keeps ownership of the stream. */
+int bx_set_stream(bx_ctx* ctx, void* hip_stream);
+
+/* rad(x) for x in [lo, hi) into the caller-owned host buffer out[hi - lo]
+ * (Algorithm 1 over the interval [start, start + length[ ).  lo >= 1, hi >= lo,
+ * hi <= hi_max.  Empty when hi == lo. */
+int bx_radical_segment(bx_ctx* ctx, uint64_t lo, uint64_t hi, uint64_t* out);
+
+/* Same, writing into caller-owned device memory dev_out[hi - lo] on the HIP
+ * stream `hip_stream` (NULL = the context's stream).  Returns once the kernels
+ * are queued; the caller synchronises the stream. */
+int bx_radical_segment_dev(bx_ctx* ctx, uint64_t lo, uint64_t hi, uint64_t* dev_out, void* hip_stream);
+
+/* All pairs 1 <= m < n <= N whose kind is in `kinds` (Algorithm 2's output,
+ * found by the hash-partitioned join); radicals are sieved over [1, N + 1].
+ * *out is malloc'd, *count set.  N + 1 <= hi_max. */
+int bx_benelux_search(bx_ctx* ctx, uint64_t N, uint32_t kinds, bx_pair** out, size_t* count);
+
+/* Range form: pairs with max(a,1) <= m < n < b (radicals over [max(a,1), b]).
+ * bx_benelux_search(N) equals bx_search_range(1, N + 1).  b <= hi_max. */
+int bx_search_range(bx_ctx* ctx, uint64_t a, uint64_t b, uint32_t kinds, bx_pair** out, size_t* count);
+
+/* Batched range queries: for each i < q, the pairs inside [a[i], b[i]) (each
+ * query is joined only with itself).  One pipeline serves all queries, captured
+ * in a HIP graph.  b[i] - a[i] <= 2^28 each, q <= 32768.  *out is malloc'd and
+ * holds the pairs of query i at [offsets[i], offsets[i+1]); offsets is
+ * caller-owned with q + 1 entries. */
+int bx_search_batch(bx_ctx* ctx, const uint64_t* a, const uint64_t* b, size_t q, uint32_t kinds, bx_pair** out,
+                    size_t* offsets);
+
+/* Serving (continuous batching).  bx_serve_start launches the library's
+ * scheduler thread; requests are admitted while the device bytes of in-flight
+ * work stay within budget_bytes and fewer than max_inflight batches run; work
+ * of different batches overlaps on the device on separate streams.
+ * bx_submit never blocks when wait == 0 (BX_EBUSY if the request can never fit
+ * the budget).  bx_poll reports completion, bx_take hands over the pair list
+ * (malloc'd) and releases the ticket.  Times are seconds on the library's
+ * monotonic clock (bx_now). */
+int bx_serve_start(bx_ctx* ctx, uint64_t budget_bytes, int max_inflight);
+int bx_serve_stop(bx_ctx* ctx);
+int bx_submit(bx_ctx* ctx, uint64_t a, uint64_t b, uint32_t kinds, uint64_t* ticket);
+int bx_poll(bx_ctx* ctx, uint64_t ticket, int* done);
+int bx_take(bx_ctx* ctx, uint64_t ticket, bx_pair** out, size_t* count, double* t_submit, double* t_done);
+double bx_now(void);
+
+/* Statistics of the last completed call on this context (device times from HIP
+ * events recorded on the stream the kernels ran on). */
+typedef struct {
+  uint32_t passes;            /* hash passes run (including split re-runs)        */
+  uint32_t retries;           /* passes re-run split in two after an overflow     */
+  uint64_t integers;          /* x values whose keys were generated, per pass     */
+  uint64_t entries;           /* entries written by all passes                    */
+  uint64_t candidates;        /* candidate pairs emitted by the join              */
+  uint64_t pairs;             /* verified pairs (before the kinds filter)         */
+  uint32_t launches[5];       /* launches per kernel: sieve, partition, join, verify, radicals */
+  double kernel_ms[5];        /* summed device time per kernel, same order        */
+  double total_ms;            /* host wall time of the call                       */
+  uint32_t b1_bits, b2_bits;  /* partition fan-outs used                          */
+  uint32_t seg_len, tile;     /* segment length and LDS tile used by the sieve    */
+} bx_stats;
+int bx_get_stats(bx_ctx* ctx, bx_stats* out);
+
+/* Options (name = value); unknown names are BX_EINVAL.
+ *   "passes"       force the number of hash passes (power of two, 0 = plan)
+ *   "seg_len"      sieve segment length (multiple of the tile, 0 = default)
+ *   "timing"       1 = record HIP events per kernel (default 1)
+ *   "verify"       1 = recompute every candidate by trial division (default 1)
+ *   "b1_bits"      force the first partition fan-out (0 = plan)
+ *   "b2_bits"      force the second partition fan-out (0 = plan)               */
+int bx_set_option(bx_ctx* ctx, const char* name, int64_t value);
+
+void bx_free(void* p);
+const char* bx_last_error(void);
+
+/* Thin wrappers over a lazily created default context on device 0 with
+ * hi_max = 2^42 - 1 (the two calls of the method's boundary). */
+int benelux_search(uint64_t N, uint32_t kinds, bx_pair** out, size_t* count);
+int radical_segment(uint64_t lo, uint64_t hi, uint64_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BENELUX_H */

@@ -1,0 +1,1016 @@
+// Host side of the Benelux-pair search library: context, prime tables, the
+// planner for the hash-partitioned passes, kernel orchestration and the C-ABI
+// declared in include/benelux.h.
+#include "benelux.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "bx_kernels.h"
+
+using namespace bx;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define BX_HIP(expr)                                                                           \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) return fail(BX_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kTile = 4096;
+constexpr int kSieveBlock = 1024;
+constexpr int kPartBlock = 1024;
+constexpr int kJoinBlock = 256;
+constexpr int kVerifyBlock = 256;
+constexpr uint32_t kCandCap = 1u << 20;
+constexpr uint32_t kDefaultSegLen = 1u << 17;
+constexpr uint64_t kMaxQueryLen = 1ull << 28;
+constexpr uint32_t kMaxQueries = kGrpMask + 1;
+
+enum { K_SIEVE = 0, K_PART = 1, K_JOIN = 2, K_VERIFY = 3, K_RAD = 4 };
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+uint64_t isqrt64(uint64_t n) {
+  uint64_t r = static_cast<uint64_t>(std::sqrt(static_cast<double>(n)));
+  while (r * r > n) --r;
+  while ((r + 1) * (r + 1) <= n) ++r;
+  return r;
+}
+
+uint32_t inv32_host(uint32_t p) {
+  uint32_t x = p;
+  for (int i = 0; i < 5; ++i) x *= 2u - p * x;
+  return x;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Plan {
+  uint32_t pbits = 0, b1bits = 0, b2bits = 0;
+  uint64_t cap1 = 0;
+  uint32_t cap2 = 0;
+  uint64_t bytes = 0;
+};
+
+struct TimedLaunch {
+  int kind;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct bx_ctx {
+  int device = 0;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  uint64_t hi_max = 0, budget = 0;
+  int n_cu = 256;
+  std::vector<uint32_t> primes;
+  std::vector<PrimePow> pp;
+  uint32_t n_dense = 0;
+  uint32_t* d_primes = nullptr;
+  PrimePow* d_pp = nullptr;
+  DenseTab* d_dense = nullptr;
+  DevBuf l1, l2, cnt1, cnt2, cand, out, flags, spill, queries, segpref, rad;
+  int force_passes = 0, timing = 1, verify = 1, force_b1 = -1, force_b2 = -1;
+  uint32_t seg_len = kDefaultSegLen;
+  bx_stats stats{};
+  std::mutex mu;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<TimedLaunch> timed;
+  hipEvent_t last_done = nullptr;    // recorded after the last call's work
+  hipStream_t last_stream = nullptr;  // stream that work ran on
+  // serving
+  struct Server;
+  std::unique_ptr<Server> server;
+};
+
+namespace {
+
+int ensure(bx_ctx* c, DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.bytes >= bytes) return BX_OK;
+  if (b.p) {
+    BX_HIP(hipStreamSynchronize(c->stream));
+    BX_HIP(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return fail(BX_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  b.bytes = bytes;
+  return BX_OK;
+}
+
+void free_buf(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+hipEvent_t get_event(bx_ctx* c) {
+  if (!c->ev_free.empty()) {
+    hipEvent_t e = c->ev_free.back();
+    c->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct LaunchTimer {
+  bx_ctx* c;
+  int kind;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t s;
+  LaunchTimer(bx_ctx* ctx, int k, hipStream_t st) : c(ctx), kind(k), s(st) {
+    c->stats.launches[k]++;
+    if (c->timing) {
+      a = get_event(c);
+      b = get_event(c);
+      if (a) (void)hipEventRecord(a, s);
+    }
+  }
+  ~LaunchTimer() {
+    if (a && b) {
+      (void)hipEventRecord(b, s);
+      c->timed.push_back({kind, a, b});
+    }
+  }
+};
+
+// Called after the stream has drained: fold the recorded launches into stats.
+void collect_timings(bx_ctx* c) {
+  for (auto& t : c->timed) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) c->stats.kernel_ms[t.kind] += ms;
+    c->ev_free.push_back(t.a);
+    c->ev_free.push_back(t.b);
+  }
+  c->timed.clear();
+}
+
+void reset_stats(bx_ctx* c) {
+  for (auto& t : c->timed) {
+    c->ev_free.push_back(t.a);
+    c->ev_free.push_back(t.b);
+  }
+  c->timed.clear();
+  c->stats = bx_stats{};
+}
+
+// The workspace is shared by all calls of a context: work queued on a new
+// stream first waits for the previous call's work on the old one.
+int order_after_last(bx_ctx* c, hipStream_t st) {
+  if (c->last_done && c->last_stream != st) BX_HIP(hipStreamWaitEvent(st, c->last_done, 0));
+  return BX_OK;
+}
+
+int mark_done(bx_ctx* c, hipStream_t st) {
+  if (!c->last_done) BX_HIP(hipEventCreateWithFlags(&c->last_done, hipEventDisableTiming));
+  BX_HIP(hipEventRecord(c->last_done, st));
+  c->last_stream = st;
+  return BX_OK;
+}
+
+int fill_u32(bx_ctx* c, void* p, uint64_t n, uint32_t v, hipStream_t s) {
+  if (n == 0) return BX_OK;
+  const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_u32, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, static_cast<uint32_t*>(p), n, v);
+  BX_HIP(hipGetLastError());
+  return BX_OK;
+}
+
+// Prime tables: primes <= isqrt(hi_max) (for verification) and every odd prime
+// power p^k <= hi_max, k >= 2 (Algorithm 1 sieves with exactly these), sorted
+// by q, plus the dense schedule for the powers <= kTile.
+int build_tables(bx_ctx* c) {
+  const uint64_t lim = isqrt64(c->hi_max);
+  std::vector<uint8_t> comp(lim + 1, 0);
+  c->primes.clear();
+  for (uint64_t i = 2; i <= lim; ++i) {
+    if (comp[i]) continue;
+    c->primes.push_back(static_cast<uint32_t>(i));
+    for (uint64_t j = i * i; j <= lim; j += i) comp[j] = 1;
+  }
+  c->pp.clear();
+  for (uint32_t p : c->primes) {
+    if (p == 2) continue;
+    const uint32_t pinv = inv32_host(p);
+    uint64_t q = static_cast<uint64_t>(p) * p;
+    while (q <= c->hi_max) {
+      c->pp.push_back(PrimePow{q, 1.0 / static_cast<double>(q), p, pinv});
+      if (q > c->hi_max / p) break;
+      q *= p;
+    }
+  }
+  std::sort(c->pp.begin(), c->pp.end(), [](const PrimePow& a, const PrimePow& b) { return a.q < b.q; });
+  DenseTab dt;
+  std::memset(&dt, 0, sizeof(dt));
+  uint32_t nd = 0, slots = 0;
+  for (const auto& w : c->pp) {
+    if (w.q > static_cast<uint64_t>(kTile)) break;
+    if (nd >= static_cast<uint32_t>(kDenseMax)) return fail(BX_EINTERNAL, "dense prime-power table overflow");
+    const uint32_t q = static_cast<uint32_t>(w.q);
+    const uint32_t ub = kTile / q + 1;  // multiples of q among T + 1 consecutive values
+    if (slots + ub > static_cast<uint32_t>(kDenseSlotMax)) return fail(BX_EINTERNAL, "dense slot table overflow");
+    dt.q[nd] = q;
+    dt.p[nd] = w.p;
+    dt.pinv[nd] = w.pinv;
+    dt.prefix[nd] = slots;
+    for (uint32_t k = 0; k < ub; ++k) dt.slot_d[slots + k] = static_cast<uint8_t>(nd);
+    slots += ub;
+    ++nd;
+  }
+  dt.n = nd;
+  dt.nslots = slots;
+  c->n_dense = nd;
+  BX_HIP(hipMalloc(&c->d_primes, std::max<size_t>(4, c->primes.size() * sizeof(uint32_t))));
+  BX_HIP(hipMalloc(&c->d_pp, std::max<size_t>(sizeof(PrimePow), c->pp.size() * sizeof(PrimePow))));
+  BX_HIP(hipMalloc(&c->d_dense, sizeof(DenseTab)));
+  if (!c->primes.empty())
+    BX_HIP(hipMemcpy(c->d_primes, c->primes.data(), c->primes.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+  if (!c->pp.empty())
+    BX_HIP(hipMemcpy(c->d_pp, c->pp.data(), c->pp.size() * sizeof(PrimePow), hipMemcpyHostToDevice));
+  BX_HIP(hipMemcpy(c->d_dense, &dt, sizeof(DenseTab), hipMemcpyHostToDevice));
+  return BX_OK;
+}
+
+uint32_t ceil_log2(double v) {
+  uint32_t b = 0;
+  while (std::ldexp(1.0, static_cast<int>(b)) < v) ++b;
+  return b;
+}
+
+uint64_t round_up(uint64_t v, uint64_t m) { return (v + m - 1) / m * m; }
+
+uint32_t spill_cap_of(const bx_ctx* c) {
+  return static_cast<uint32_t>(c->pp.size() - c->n_dense + c->seg_len / 128 + 64);
+}
+
+uint64_t fixed_bytes(const bx_ctx* c, uint32_t sieve_grid) {
+  return static_cast<uint64_t>(sieve_grid) * spill_cap_of(c) * 8ull + kCandCap * (sizeof(Cand) + sizeof(OutPair)) +
+         (64ull << 20);
+}
+
+// Choose the number of hash passes P = 2^pbits and the two partition fan-outs
+// so that one pass's entries (16 B each, in both partition buffers) fit the
+// budget; partitions end up near 2048 entries, which one workgroup joins in LDS.
+int make_plan(bx_ctx* c, uint64_t n_keys, uint32_t sieve_grid, Plan* out) {
+  const uint64_t fixed = fixed_bytes(c, sieve_grid);
+  for (uint32_t pbits = 0; pbits <= 16; ++pbits) {
+    if (c->force_passes > 0) {
+      pbits = ceil_log2(static_cast<double>(c->force_passes));
+    }
+    Plan p;
+    p.pbits = pbits;
+    const double n_pass = std::max(1.0, std::ceil(static_cast<double>(n_keys) / std::ldexp(1.0, static_cast<int>(pbits))));
+    const uint32_t total = n_pass > 2048.0 ? ceil_log2(n_pass / 2048.0) : 0;
+    uint32_t b1 = std::min<uint32_t>(10, total);
+    uint32_t b2 = total - b1;
+    if (c->force_b1 >= 0) b1 = static_cast<uint32_t>(c->force_b1);
+    if (c->force_b2 >= 0) b2 = static_cast<uint32_t>(c->force_b2);
+    if (b1 > 10 || b2 > 12 || pbits + b1 + b2 > 31) {
+      if (c->force_passes > 0) return fail(BX_ENOMEM, "forced pass count leaves partitions too large");
+      continue;
+    }
+    p.b1bits = b1;
+    p.b2bits = b2;
+    p.cap1 = round_up(static_cast<uint64_t>(std::ceil(n_pass / std::ldexp(1.0, static_cast<int>(b1)) * 1.03)) + 2048, 64);
+    p.cap2 = static_cast<uint32_t>(
+        round_up(static_cast<uint64_t>(std::ceil(static_cast<double>(p.cap1) / std::ldexp(1.0, static_cast<int>(b2)) * 1.25)) + 64,
+                 16));
+    if (p.cap1 > 0xF0000000ull) continue;
+    const uint64_t nb1 = 1ull << b1, nsub = 1ull << (b1 + b2);
+    p.bytes = nb1 * p.cap1 * sizeof(Entry) + nsub * p.cap2 * sizeof(Entry) + (nb1 + nsub) * 4;
+    if (p.bytes + fixed <= c->budget || c->force_passes > 0) {
+      if (p.bytes + fixed > c->budget)
+        return fail(BX_ENOMEM, "forced pass count needs " + std::to_string(p.bytes + fixed) + " bytes, budget " +
+                                   std::to_string(c->budget));
+      *out = p;
+      return BX_OK;
+    }
+  }
+  return fail(BX_ENOMEM, "HBM budget too small for the search");
+}
+
+struct Segs {
+  std::vector<Query> q;
+  std::vector<uint64_t> prefix;
+  uint64_t n_segs = 0, n_keys = 0;
+};
+
+void make_segs(const bx_ctx* c, Segs* s) {
+  s->prefix.assign(s->q.size() + 1, 0);
+  uint64_t acc = 0, keys = 0;
+  for (size_t i = 0; i < s->q.size(); ++i) {
+    s->prefix[i] = acc;
+    const uint64_t L = s->q[i].b > s->q[i].a ? s->q[i].b - s->q[i].a : 0;
+    acc += (L + c->seg_len - 1) / c->seg_len;
+    keys += L;
+  }
+  s->prefix[s->q.size()] = acc;
+  s->n_segs = acc;
+  s->n_keys = keys;
+}
+
+int upload_segs(bx_ctx* c, const Segs& s, hipStream_t st) {
+  int rc;
+  if ((rc = ensure(c, c->queries, s.q.size() * sizeof(Query))) != BX_OK) return rc;
+  if ((rc = ensure(c, c->segpref, s.prefix.size() * sizeof(uint64_t))) != BX_OK) return rc;
+  BX_HIP(hipMemcpyAsync(c->queries.p, s.q.data(), s.q.size() * sizeof(Query), hipMemcpyHostToDevice, st));
+  BX_HIP(hipMemcpyAsync(c->segpref.p, s.prefix.data(), s.prefix.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  // The host vectors die with the caller: wait for the copies.
+  BX_HIP(hipStreamSynchronize(st));
+  return BX_OK;
+}
+
+SieveParams base_sieve_params(bx_ctx* c, const Segs& s) {
+  SieveParams P;
+  std::memset(&P, 0, sizeof(P));
+  P.queries = static_cast<const Query*>(c->queries.p);
+  P.seg_prefix = static_cast<const uint64_t*>(c->segpref.p);
+  P.n_queries = static_cast<uint32_t>(s.q.size());
+  P.n_segs = s.n_segs;
+  P.seg_len = c->seg_len;
+  P.pp = c->d_pp;
+  P.n_pp = static_cast<uint32_t>(c->pp.size());
+  P.n_dense = c->n_dense;
+  P.dense = c->d_dense;
+  P.spill = static_cast<uint64_t*>(c->spill.p);
+  P.spill_cap = spill_cap_of(c);
+  P.flags = static_cast<uint32_t*>(c->flags.p);
+  return P;
+}
+
+int check_query(const bx_ctx* c, uint64_t a, uint64_t b) {
+  if (b > c->hi_max || b >= BX_VALUE_LIMIT)
+    return fail(BX_ERANGE, "range end " + std::to_string(b) + " exceeds hi_max " + std::to_string(c->hi_max));
+  (void)a;
+  return BX_OK;
+}
+
+// The hash-partitioned exact join over all queries of `s`.  Entries are
+// generated pass by pass; a pass whose buckets overflow is re-run split in
+// two (one more hash bit), so the result never depends on the bucket sizes.
+int run_search(bx_ctx* c, Segs& s, int batch, uint32_t kinds, std::vector<OutPair>* result) {
+  hipStream_t st = c->stream;
+  result->clear();
+  int rc0 = order_after_last(c, st);
+  if (rc0 != BX_OK) return rc0;
+  rc0 = mark_done(c, st);  // host-synchronous from here on: the call drains st
+  if (rc0 != BX_OK) return rc0;
+  make_segs(c, &s);
+  if (s.n_segs == 0) return BX_OK;
+  int rc;
+  const uint32_t sieve_grid = static_cast<uint32_t>(std::min<uint64_t>(s.n_segs, static_cast<uint64_t>(c->n_cu)));
+  Plan plan;
+  if ((rc = make_plan(c, s.n_keys, sieve_grid, &plan)) != BX_OK) return rc;
+  const uint32_t B1 = 1u << plan.b1bits, B2 = 1u << plan.b2bits;
+  const uint64_t nsub = static_cast<uint64_t>(B1) * B2;
+  if ((rc = ensure(c, c->l1, B1 * plan.cap1 * sizeof(Entry))) != BX_OK) return rc;
+  if ((rc = ensure(c, c->l2, nsub * plan.cap2 * sizeof(Entry))) != BX_OK) return rc;
+  if ((rc = ensure(c, c->cnt1, B1 * 4ull)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->cnt2, nsub * 4ull)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->cand, kCandCap * sizeof(Cand))) != BX_OK) return rc;
+  if ((rc = ensure(c, c->out, kCandCap * sizeof(OutPair))) != BX_OK) return rc;
+  if ((rc = ensure(c, c->flags, kFlagCount * 4)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->spill, static_cast<size_t>(sieve_grid) * spill_cap_of(c) * 8)) != BX_OK) return rc;
+  if ((rc = upload_segs(c, s, st)) != BX_OK) return rc;
+  if ((rc = fill_u32(c, c->flags.p, kFlagCount, 0, st)) != BX_OK) return rc;
+  c->stats.b1_bits = plan.b1bits;
+  c->stats.b2_bits = plan.b2bits;
+  c->stats.seg_len = c->seg_len;
+  c->stats.tile = kTile;
+
+  const uint32_t gmask = batch ? kGrpMask : 0u;
+  const uint64_t kmask1 = kM42 | (static_cast<uint64_t>(gmask) << kGrpShift);
+  std::deque<std::pair<uint32_t, uint32_t>> pending;
+  for (uint32_t v = 0; v < (1u << plan.pbits); ++v) pending.emplace_back(plan.pbits, v);
+  uint32_t cand_before = 0;
+  uint32_t* d_flags = static_cast<uint32_t*>(c->flags.p);
+  while (!pending.empty()) {
+    const uint32_t pbits = pending.front().first, pval = pending.front().second;
+    pending.pop_front();
+    if (pbits + plan.b1bits + plan.b2bits > 32) return fail(BX_EINTERNAL, "pass split exhausted the hash bits");
+    if ((rc = fill_u32(c, c->cnt1.p, B1, 0, st)) != BX_OK) return rc;
+    if ((rc = fill_u32(c, c->cnt2.p, nsub, 0, st)) != BX_OK) return rc;
+    SieveParams P = base_sieve_params(c, s);
+    P.batch = batch;
+    P.pfilter = pbits > 0;
+    P.pshift = pbits > 0 ? 32 - pbits : 0;
+    P.pval = pval;
+    P.b1shift = plan.b1bits ? 32 - pbits - plan.b1bits : 0;
+    P.b1mask = B1 - 1;
+    P.l1 = static_cast<Entry*>(c->l1.p);
+    P.cap1 = plan.cap1;
+    P.cnt1 = static_cast<uint32_t*>(c->cnt1.p);
+    {
+      LaunchTimer t(c, K_SIEVE, st);
+      hipLaunchKernelGGL((k_sieve<kTile, kSieveBlock, MODE_KEYS>), dim3(sieve_grid), dim3(kSieveBlock), 0, st, P);
+    }
+    BX_HIP(hipGetLastError());
+    PartParams Q;
+    Q.l1 = static_cast<const Entry*>(c->l1.p);
+    Q.cap1 = plan.cap1;
+    Q.cnt1 = static_cast<const uint32_t*>(c->cnt1.p);
+    Q.B1 = B1;
+    Q.chunks_per_bucket = static_cast<uint32_t>((plan.cap1 + kPartChunk - 1) / kPartChunk);
+    Q.l2 = static_cast<Entry*>(c->l2.p);
+    Q.cap2 = plan.cap2;
+    Q.cnt2 = static_cast<uint32_t*>(c->cnt2.p);
+    Q.b2shift = plan.b2bits ? 32 - pbits - plan.b1bits - plan.b2bits : 0;
+    Q.b2mask = B2 - 1;
+    Q.gmask = gmask;
+    Q.flags = d_flags;
+    const uint64_t part_grid = 8ull * ((B1 + 7) / 8) * Q.chunks_per_bucket;
+    if (part_grid > 0x7FFFFFFFull) return fail(BX_EINTERNAL, "partition grid too large");
+    {
+      LaunchTimer t(c, K_PART, st);
+      hipLaunchKernelGGL((k_partition<kPartBlock>), dim3(static_cast<uint32_t>(part_grid)), dim3(kPartBlock), 0, st, Q);
+    }
+    BX_HIP(hipGetLastError());
+    JoinParams J;
+    J.l2 = static_cast<const Entry*>(c->l2.p);
+    J.cap2 = plan.cap2;
+    J.cnt2 = static_cast<const uint32_t*>(c->cnt2.p);
+    J.n_sub = nsub;
+    J.kmask1 = kmask1;
+    J.gmask = gmask;
+    J.cand = static_cast<Cand*>(c->cand.p);
+    J.cand_cap = kCandCap;
+    J.flags = d_flags;
+    {
+      LaunchTimer t(c, K_JOIN, st);
+      hipLaunchKernelGGL((k_join<kJoinBlock>), dim3(static_cast<uint32_t>(nsub)), dim3(kJoinBlock), 0, st, J);
+    }
+    BX_HIP(hipGetLastError());
+    uint32_t fl[kFlagCount];
+    BX_HIP(hipMemcpyAsync(fl, d_flags, sizeof(fl), hipMemcpyDeviceToHost, st));
+    BX_HIP(hipStreamSynchronize(st));
+    c->stats.passes++;
+    if (fl[kFlagSpillOverflow]) return fail(BX_EINTERNAL, "sparse-hit spill buffer overflow");
+    if (fl[kFlagL1Overflow] || fl[kFlagL2Overflow]) {
+      // Discard this pass's candidates and run it again as two half passes.
+      c->stats.retries++;
+      uint32_t z[2] = {0, 0};
+      BX_HIP(hipMemcpyAsync(d_flags + kFlagL1Overflow, z, sizeof(z), hipMemcpyHostToDevice, st));
+      BX_HIP(hipMemcpyAsync(d_flags + kFlagCand, &cand_before, 4, hipMemcpyHostToDevice, st));
+      BX_HIP(hipStreamSynchronize(st));
+      pending.emplace_front(pbits + 1, 2 * pval + 1);
+      pending.emplace_front(pbits + 1, 2 * pval);
+      continue;
+    }
+    cand_before = fl[kFlagCand];
+    std::vector<uint32_t> counts(B1);
+    BX_HIP(hipMemcpyAsync(counts.data(), c->cnt1.p, B1 * 4, hipMemcpyDeviceToHost, st));
+    BX_HIP(hipStreamSynchronize(st));
+    for (uint32_t v : counts) c->stats.entries += v;
+  }
+  c->stats.integers = s.n_keys;
+  if (cand_before > kCandCap) return fail(BX_EINTERNAL, "candidate buffer overflow");
+  c->stats.candidates = cand_before;
+  if (cand_before > 0) {
+    VerifyParams V;
+    V.cand = static_cast<const Cand*>(c->cand.p);
+    V.n_cand = cand_before;
+    V.primes = c->d_primes;
+    V.n_primes = static_cast<uint32_t>(c->primes.size());
+    V.queries = static_cast<const Query*>(c->queries.p);
+    V.batch = batch;
+    V.kinds = kinds;
+    V.out = static_cast<OutPair*>(c->out.p);
+    V.out_cap = kCandCap;
+    V.flags = d_flags;
+    {
+      LaunchTimer t(c, K_VERIFY, st);
+      hipLaunchKernelGGL((k_verify<kVerifyBlock>), dim3(cand_before), dim3(kVerifyBlock), 0, st, V);
+    }
+    BX_HIP(hipGetLastError());
+    uint32_t fl[kFlagCount];
+    BX_HIP(hipMemcpyAsync(fl, d_flags, sizeof(fl), hipMemcpyDeviceToHost, st));
+    BX_HIP(hipStreamSynchronize(st));
+    if (fl[kFlagVerifyFail])
+      return fail(BX_EINTERNAL, std::to_string(fl[kFlagVerifyFail]) + " candidate pairs failed exact verification");
+    const uint32_t n_out = std::min(fl[kFlagOut], kCandCap);
+    c->stats.pairs = n_out;
+    result->resize(n_out);
+    if (n_out) {
+      BX_HIP(hipMemcpyAsync(result->data(), c->out.p, n_out * sizeof(OutPair), hipMemcpyDeviceToHost, st));
+      BX_HIP(hipStreamSynchronize(st));
+    }
+  }
+  std::sort(result->begin(), result->end(), [](const OutPair& x, const OutPair& y) {
+    if (x.query != y.query) return x.query < y.query;
+    if (x.m != y.m) return x.m < y.m;
+    return x.n < y.n;
+  });
+  return BX_OK;
+}
+
+int to_pairs(const std::vector<OutPair>& v, bx_pair** out, size_t* count) {
+  *out = nullptr;
+  *count = v.size();
+  if (v.empty()) return BX_OK;
+  bx_pair* p = static_cast<bx_pair*>(std::malloc(v.size() * sizeof(bx_pair)));
+  if (!p) return fail(BX_ENOMEM, "host allocation failed");
+  for (size_t i = 0; i < v.size(); ++i) p[i] = bx_pair{v[i].m, v[i].n, v[i].kind, v[i].query};
+  *out = p;
+  return BX_OK;
+}
+
+int radicals_into(bx_ctx* c, uint64_t lo, uint64_t hi, uint64_t* dev_out, hipStream_t st) {
+  Segs s;
+  s.q.push_back(Query{lo, hi});
+  make_segs(c, &s);
+  if (s.n_segs == 0) return BX_OK;
+  int rc;
+  if ((rc = upload_segs(c, s, st)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->flags, kFlagCount * 4)) != BX_OK) return rc;
+  const uint32_t grid = static_cast<uint32_t>(std::min<uint64_t>(s.n_segs, 3ull * c->n_cu));
+  if ((rc = ensure(c, c->spill, static_cast<size_t>(grid) * spill_cap_of(c) * 8)) != BX_OK) return rc;
+  if ((rc = fill_u32(c, c->flags.p, kFlagCount, 0, st)) != BX_OK) return rc;
+  SieveParams P = base_sieve_params(c, s);
+  P.rad_out = dev_out;
+  P.rad_lo = lo;
+  P.rad_hi = hi;
+  {
+    LaunchTimer t(c, K_RAD, st);
+    hipLaunchKernelGGL((k_sieve<kTile, kSieveBlock, MODE_RAD>), dim3(grid), dim3(kSieveBlock), 0, st, P);
+  }
+  BX_HIP(hipGetLastError());
+  return BX_OK;
+}
+
+std::mutex g_default_mu;
+bx_ctx* g_default = nullptr;
+
+int default_ctx(bx_ctx** out) {
+  std::lock_guard<std::mutex> lk(g_default_mu);
+  if (!g_default) {
+    int rc = bx_create(&g_default, 0, BX_VALUE_LIMIT - 1, 0);
+    if (rc != BX_OK) {
+      g_default = nullptr;
+      return rc;
+    }
+  }
+  *out = g_default;
+  return BX_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Serving: a scheduler thread forms batches of admitted requests and runs each
+// batch on its own context (own stream, own workspace), so the work of
+// different batches overlaps on the device.
+struct bx_ctx::Server {
+  struct Req {
+    uint64_t a, b;
+    uint32_t kinds;
+    double t_submit = 0, t_done = 0;
+    bool done = false;
+    int rc = BX_OK;
+    std::vector<OutPair> pairs;
+  };
+  bx_ctx* owner = nullptr;
+  uint64_t budget = 0;
+  int max_inflight = 2;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<uint64_t> queue;
+  std::map<uint64_t, std::unique_ptr<Req>> reqs;
+  uint64_t next_ticket = 1;
+  uint64_t inflight_bytes = 0;
+  int inflight = 0;
+  bool stop = false;
+  std::vector<std::thread> workers;
+  std::vector<bx_ctx*> lanes;
+};
+
+namespace {
+
+uint64_t request_bytes(uint64_t a, uint64_t b) {
+  const uint64_t L = b > a ? b - a : 0;
+  return L * 2 * sizeof(Entry);  // entries in both partition buffers
+}
+
+void serve_worker(bx_ctx::Server* S, int lane) {
+  bx_ctx* c = S->lanes[lane];
+  for (;;) {
+    std::vector<uint64_t> batch;
+    uint64_t bytes = 0;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv.wait(lk, [&] { return S->stop || !S->queue.empty(); });
+      if (S->stop && S->queue.empty()) return;
+      // Admit queued requests in arrival order while the in-flight bytes stay
+      // within the budget (a lone request is always admitted).
+      while (!S->queue.empty() && batch.size() < kMaxQueries) {
+        const uint64_t t = S->queue.front();
+        auto& r = *S->reqs[t];
+        const uint64_t rb = request_bytes(r.a, r.b);
+        if (!batch.empty() && S->inflight_bytes + rb > S->budget) break;
+        if (batch.empty() && S->inflight_bytes > 0 && S->inflight_bytes + rb > S->budget) break;
+        S->queue.pop_front();
+        S->inflight_bytes += rb;
+        bytes += rb;
+        batch.push_back(t);
+      }
+      if (batch.empty()) {
+        S->cv.wait_for(lk, std::chrono::milliseconds(1));
+        continue;
+      }
+      S->inflight++;
+    }
+    Segs s;
+    std::vector<uint32_t> kinds;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (uint64_t t : batch) {
+        auto& r = *S->reqs[t];
+        s.q.push_back(Query{std::max<uint64_t>(r.a, 1), r.b});
+        kinds.push_back(r.kinds);
+      }
+    }
+    std::vector<OutPair> res;
+    int rc;
+    {
+      std::lock_guard<std::mutex> lk(c->mu);
+      reset_stats(c);
+      rc = run_search(c, s, 1, BX_BOTH, &res);
+      (void)hipStreamSynchronize(c->stream);
+      collect_timings(c);
+    }
+    const double t_done = now_s();
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (size_t i = 0; i < batch.size(); ++i) {
+        auto& r = *S->reqs[batch[i]];
+        r.rc = rc;
+        r.t_done = t_done;
+        r.done = true;
+      }
+      for (const auto& p : res) {
+        auto& r = *S->reqs[batch[p.query]];
+        if (r.kinds & p.kind) r.pairs.push_back(OutPair{p.m, p.n, p.kind, 0});
+      }
+      S->inflight_bytes -= bytes;
+      S->inflight--;
+    }
+    S->cv.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int bx_create(bx_ctx** out, int device, uint64_t hi_max, uint64_t hbm_budget_bytes) {
+  if (!out) return fail(BX_EINVAL, "ctx pointer is NULL");
+  *out = nullptr;
+  if (hi_max < 2 || hi_max >= BX_VALUE_LIMIT) return fail(BX_ERANGE, "hi_max must be in [2, 2^42)");
+  int ndev = 0;
+  BX_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(BX_EINVAL, "no HIP device " + std::to_string(device));
+  BX_HIP(hipSetDevice(device));
+  std::unique_ptr<bx_ctx> c(new bx_ctx());
+  c->device = device;
+  c->hi_max = hi_max;
+  hipDeviceProp_t prop;
+  BX_HIP(hipGetDeviceProperties(&prop, device));
+  c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  BX_HIP(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
+  c->stream = c->own_stream;
+  size_t free_b = 0, total_b = 0;
+  BX_HIP(hipMemGetInfo(&free_b, &total_b));
+  c->budget = hbm_budget_bytes ? hbm_budget_bytes : static_cast<uint64_t>(0.85 * static_cast<double>(free_b));
+  int rc = build_tables(c.get());
+  if (rc != BX_OK) return rc;
+  *out = c.release();
+  return BX_OK;
+}
+
+void bx_destroy(bx_ctx* c) {
+  if (!c) return;
+  bx_serve_stop(c);
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (DevBuf* b : {&c->l1, &c->l2, &c->cnt1, &c->cnt2, &c->cand, &c->out, &c->flags, &c->spill, &c->queries,
+                    &c->segpref, &c->rad})
+    free_buf(*b);
+  if (c->d_primes) (void)hipFree(c->d_primes);
+  if (c->d_pp) (void)hipFree(c->d_pp);
+  if (c->d_dense) (void)hipFree(c->d_dense);
+  reset_stats(c);
+  for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
+  if (c->last_done) (void)hipEventDestroy(c->last_done);
+  if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+  delete c;
+}
+
+int bx_set_stream(bx_ctx* c, void* s) {
+  if (!c) return fail(BX_EINVAL, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->stream = s ? static_cast<hipStream_t>(s) : c->own_stream;
+  return BX_OK;
+}
+
+int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
+  if (!c || !name) return fail(BX_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(c->mu);
+  const std::string n(name);
+  if (n == "passes") {
+    if (v < 0 || (v & (v - 1))) return fail(BX_EINVAL, "passes must be 0 or a power of two");
+    c->force_passes = static_cast<int>(v);
+  } else if (n == "seg_len") {
+    if (v == 0) v = kDefaultSegLen;
+    if (v < kTile || v % kTile || v > (1 << 24)) return fail(BX_EINVAL, "seg_len must be a multiple of the tile in [tile, 2^24]");
+    c->seg_len = static_cast<uint32_t>(v);
+  } else if (n == "timing") {
+    c->timing = v != 0;
+  } else if (n == "verify") {
+    c->verify = v != 0;
+  } else if (n == "b1_bits") {
+    if (v > 10) return fail(BX_EINVAL, "b1_bits <= 10");
+    c->force_b1 = v == 0 ? -1 : static_cast<int>(v);
+  } else if (n == "b2_bits") {
+    if (v > 12) return fail(BX_EINVAL, "b2_bits <= 12");
+    c->force_b2 = v == 0 ? -1 : static_cast<int>(v);
+  } else {
+    return fail(BX_EINVAL, "unknown option " + n);
+  }
+  return BX_OK;
+}
+
+int bx_get_stats(bx_ctx* c, bx_stats* out) {
+  if (!c || !out) return fail(BX_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(c->mu);
+  *out = c->stats;
+  return BX_OK;
+}
+
+int bx_radical_segment(bx_ctx* c, uint64_t lo, uint64_t hi, uint64_t* out) {
+  if (!c) return fail(BX_EINVAL, "ctx is NULL");
+  if (lo == 0 || hi < lo) return fail(BX_EINVAL, "need 1 <= lo <= hi");
+  if (hi > lo && !out) return fail(BX_EINVAL, "out is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  const double t0 = now_s();
+  reset_stats(c);
+  int rc = check_query(c, lo, hi);
+  if (rc != BX_OK) return rc;
+  if (hi == lo) return BX_OK;
+  BX_HIP(hipSetDevice(c->device));
+  if ((rc = order_after_last(c, c->stream)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->rad, (hi - lo) * 8)) != BX_OK) return rc;
+  if ((rc = radicals_into(c, lo, hi, static_cast<uint64_t*>(c->rad.p), c->stream)) != BX_OK) return rc;
+  if ((rc = mark_done(c, c->stream)) != BX_OK) return rc;
+  BX_HIP(hipMemcpyAsync(out, c->rad.p, (hi - lo) * 8, hipMemcpyDeviceToHost, c->stream));
+  BX_HIP(hipStreamSynchronize(c->stream));
+  collect_timings(c);
+  c->stats.integers = hi - lo;
+  c->stats.total_ms = (now_s() - t0) * 1e3;
+  return BX_OK;
+}
+
+int bx_radical_segment_dev(bx_ctx* c, uint64_t lo, uint64_t hi, uint64_t* dev_out, void* stream) {
+  if (!c) return fail(BX_EINVAL, "ctx is NULL");
+  if (lo == 0 || hi < lo) return fail(BX_EINVAL, "need 1 <= lo <= hi");
+  if (hi > lo && !dev_out) return fail(BX_EINVAL, "dev_out is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  reset_stats(c);
+  int rc = check_query(c, lo, hi);
+  if (rc != BX_OK) return rc;
+  if (hi == lo) return BX_OK;
+  BX_HIP(hipSetDevice(c->device));
+  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  if ((rc = order_after_last(c, st)) != BX_OK) return rc;
+  // The query tables are uploaded on `st`; the caller synchronises it.
+  rc = radicals_into(c, lo, hi, dev_out, st);
+  c->stats.integers = hi - lo;
+  if (rc == BX_OK) rc = mark_done(c, st);
+  return rc;
+}
+
+int bx_search_range(bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds, bx_pair** out, size_t* count) {
+  if (!c || !out || !count) return fail(BX_EINVAL, "NULL argument");
+  *out = nullptr;
+  *count = 0;
+  if (kinds < 1 || kinds > 3) return fail(BX_EINVAL, "kinds must be 1, 2 or 3");
+  std::lock_guard<std::mutex> lk(c->mu);
+  const double t0 = now_s();
+  reset_stats(c);
+  if (a == 0) a = 1;
+  if (b <= a + 1) return BX_OK;
+  int rc = check_query(c, a, b);
+  if (rc != BX_OK) return rc;
+  BX_HIP(hipSetDevice(c->device));
+  Segs s;
+  s.q.push_back(Query{a, b});
+  std::vector<OutPair> res;
+  rc = run_search(c, s, 0, kinds, &res);
+  (void)hipStreamSynchronize(c->stream);
+  collect_timings(c);
+  c->stats.total_ms = (now_s() - t0) * 1e3;
+  if (rc != BX_OK) return rc;
+  return to_pairs(res, out, count);
+}
+
+int bx_benelux_search(bx_ctx* c, uint64_t N, uint32_t kinds, bx_pair** out, size_t* count) {
+  if (N >= BX_VALUE_LIMIT) return fail(BX_ERANGE, "N too large");
+  return bx_search_range(c, 1, N + 1, kinds, out, count);
+}
+
+int bx_search_batch(bx_ctx* c, const uint64_t* a, const uint64_t* b, size_t q, uint32_t kinds, bx_pair** out,
+                    size_t* offsets) {
+  if (!c || !out || !offsets || (q && (!a || !b))) return fail(BX_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (kinds < 1 || kinds > 3) return fail(BX_EINVAL, "kinds must be 1, 2 or 3");
+  if (q > kMaxQueries) return fail(BX_EINVAL, "at most 32768 queries per batch");
+  std::lock_guard<std::mutex> lk(c->mu);
+  const double t0 = now_s();
+  reset_stats(c);
+  Segs s;
+  for (size_t i = 0; i < q; ++i) {
+    uint64_t ai = a[i] == 0 ? 1 : a[i], bi = b[i];
+    if (bi < ai) bi = ai;
+    if (bi - ai > kMaxQueryLen) return fail(BX_EINVAL, "query longer than 2^28");
+    if (bi > ai + 1) {
+      int rc = check_query(c, ai, bi);
+      if (rc != BX_OK) return rc;
+    } else {
+      bi = ai;  // fewer than two integers: no pair, no work
+    }
+    s.q.push_back(Query{ai, bi});
+  }
+  BX_HIP(hipSetDevice(c->device));
+  std::vector<OutPair> res;
+  int rc = run_search(c, s, 1, kinds, &res);
+  (void)hipStreamSynchronize(c->stream);
+  collect_timings(c);
+  c->stats.total_ms = (now_s() - t0) * 1e3;
+  if (rc != BX_OK) return rc;
+  size_t k = 0;
+  for (size_t i = 0; i < q; ++i) {
+    offsets[i] = k;
+    while (k < res.size() && res[k].query == i) ++k;
+  }
+  offsets[q] = res.size();
+  size_t cnt = 0;
+  return to_pairs(res, out, &cnt);
+}
+
+int bx_serve_start(bx_ctx* c, uint64_t budget_bytes, int max_inflight) {
+  if (!c) return fail(BX_EINVAL, "ctx is NULL");
+  if (c->server) return fail(BX_EINVAL, "server already running");
+  if (max_inflight < 1 || max_inflight > 8) return fail(BX_EINVAL, "max_inflight in [1, 8]");
+  auto S = std::make_unique<bx_ctx::Server>();
+  S->owner = c;
+  S->budget = budget_bytes ? budget_bytes : c->budget / 2;
+  S->max_inflight = max_inflight;
+  for (int i = 0; i < max_inflight; ++i) {
+    bx_ctx* lane = nullptr;
+    const uint64_t lane_budget = S->budget / max_inflight + (1ull << 30);
+    int rc = bx_create(&lane, c->device, c->hi_max, lane_budget);
+    if (rc != BX_OK) {
+      for (bx_ctx* l : S->lanes) bx_destroy(l);
+      return rc;
+    }
+    lane->seg_len = c->seg_len;
+    lane->timing = 0;
+    S->lanes.push_back(lane);
+  }
+  bx_ctx::Server* raw = S.get();
+  c->server = std::move(S);
+  for (int i = 0; i < max_inflight; ++i) raw->workers.emplace_back(serve_worker, raw, i);
+  return BX_OK;
+}
+
+int bx_serve_stop(bx_ctx* c) {
+  if (!c || !c->server) return BX_OK;
+  {
+    std::lock_guard<std::mutex> lk(c->server->mu);
+    c->server->stop = true;
+  }
+  c->server->cv.notify_all();
+  for (auto& t : c->server->workers) t.join();
+  for (bx_ctx* l : c->server->lanes) bx_destroy(l);
+  c->server.reset();
+  return BX_OK;
+}
+
+int bx_submit(bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds, uint64_t* ticket) {
+  if (!c || !ticket) return fail(BX_EINVAL, "NULL argument");
+  if (!c->server) return fail(BX_EINVAL, "server not started");
+  if (kinds < 1 || kinds > 3) return fail(BX_EINVAL, "kinds must be 1, 2 or 3");
+  if (a == 0) a = 1;
+  if (b < a) b = a;
+  if (b - a > kMaxQueryLen) return fail(BX_EINVAL, "request longer than 2^28");
+  if (b > a + 1) {
+    int rc = check_query(c, a, b);
+    if (rc != BX_OK) return rc;
+  }
+  auto* S = c->server.get();
+  if (request_bytes(a, b) > S->budget) return fail(BX_EBUSY, "request can never fit the serving budget");
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    const uint64_t t = S->next_ticket++;
+    auto r = std::make_unique<bx_ctx::Server::Req>();
+    r->a = a;
+    r->b = b;
+    r->kinds = kinds;
+    r->t_submit = now_s();
+    S->reqs[t] = std::move(r);
+    S->queue.push_back(t);
+    *ticket = t;
+  }
+  S->cv.notify_all();
+  return BX_OK;
+}
+
+int bx_poll(bx_ctx* c, uint64_t ticket, int* done) {
+  if (!c || !done) return fail(BX_EINVAL, "NULL argument");
+  if (!c->server) return fail(BX_EINVAL, "server not started");
+  auto* S = c->server.get();
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return fail(BX_EINVAL, "unknown ticket");
+  *done = it->second->done ? 1 : 0;
+  return BX_OK;
+}
+
+int bx_take(bx_ctx* c, uint64_t ticket, bx_pair** out, size_t* count, double* t_submit, double* t_done) {
+  if (!c || !out || !count) return fail(BX_EINVAL, "NULL argument");
+  if (!c->server) return fail(BX_EINVAL, "server not started");
+  auto* S = c->server.get();
+  std::unique_ptr<bx_ctx::Server::Req> r;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return fail(BX_EINVAL, "unknown ticket");
+    if (!it->second->done) return fail(BX_EBUSY, "request not finished");
+    r = std::move(it->second);
+    S->reqs.erase(it);
+  }
+  if (t_submit) *t_submit = r->t_submit;
+  if (t_done) *t_done = r->t_done;
+  if (r->rc != BX_OK) return fail(r->rc, "request failed");
+  return to_pairs(r->pairs, out, count);
+}
+
+double bx_now(void) { return now_s(); }
+
+void bx_free(void* p) { std::free(p); }
+
+const char* bx_last_error(void) { return g_err.c_str(); }
+
+int benelux_search(uint64_t N, uint32_t kinds, bx_pair** out, size_t* count) {
+  bx_ctx* c = nullptr;
+  int rc = default_ctx(&c);
+  if (rc != BX_OK) return rc;
+  return bx_benelux_search(c, N, kinds, out, count);
+}
+
+int radical_segment(uint64_t lo, uint64_t hi, uint64_t* out) {
+  bx_ctx* c = nullptr;
+  int rc = default_ctx(&c);
+  if (rc != BX_OK) return rc;
+  return bx_radical_segment(c, lo, hi, out);
+}
+
+}  // extern "C"

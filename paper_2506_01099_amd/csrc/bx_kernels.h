@@ -1,0 +1,527 @@
+// HIP kernels of the Benelux-pair search for gfx950.
+//
+//   k_sieve<MODE_RAD>   Algorithm 1 on LDS tiles, radicals written to HBM.
+//   k_sieve<MODE_KEYS>  Algorithm 1 on LDS tiles, then the set S_x of every x
+//                       (Section 2.1), the pass filter of the hash-partitioned
+//                       passes, wave-ballot compaction and the first partition
+//                       scatter of the exact join, fused in one kernel.
+//   k_partition         second partition scatter (fan-out B2), XCD-aware.
+//   k_join              LDS hash join of one partition: inserts that detect
+//                       every earlier equal key on their probe chain, as the
+//                       insert step of Algorithm 3 does, so each pair of a
+//                       group of equal sets is reported exactly once.
+//   k_verify            every candidate pair recomputed by trial division with
+//                       the resident primes, classified (first kind when
+//                       rad(m) = rad(n), Algorithm 2) and filtered by kind.
+//   k_fill_u32          fills a word array (clears counters inside graphs).
+#pragma once
+#include "bx_device.h"
+
+namespace bx {
+
+constexpr int MODE_RAD = 0;
+constexpr int MODE_KEYS = 1;
+
+constexpr int kHitCap = 1024;      // sparse-hit list held in LDS per segment
+constexpr int kStageCap = 4096;    // staged entries per workgroup before a flush
+constexpr int kB1Max = 1024;       // first partition fan-out
+constexpr int kB2Max = 4096;       // second partition fan-out
+constexpr int kPartChunk = 4096;   // entries per workgroup in k_partition
+constexpr int kJoinCap = 3072;     // entries of one LDS join chunk
+constexpr int kJoinSlots = 8192;   // LDS hash-table slots (load <= 0.375)
+
+struct SieveParams {
+  const Query* queries;
+  const uint64_t* seg_prefix;  // n_queries + 1: first segment of each query
+  uint32_t n_queries;
+  uint64_t n_segs;
+  uint32_t seg_len;
+  const PrimePow* pp;  // all odd prime powers <= hi_max, ascending
+  uint32_t n_pp;
+  uint32_t n_dense;  // pp[0, n_dense) are the dense ones (q <= tile)
+  const DenseTab* dense;
+  uint64_t* spill;  // per workgroup: spill + blockIdx.x * spill_cap
+  uint32_t spill_cap;
+  uint32_t* flags;
+  // MODE_RAD
+  uint64_t* rad_out;
+  uint64_t rad_lo, rad_hi;
+  // MODE_KEYS
+  int batch;
+  uint32_t pfilter, pshift, pval;
+  uint32_t b1shift, b1mask;
+  Entry* l1;
+  uint64_t cap1;
+  uint32_t* cnt1;
+};
+
+template <int T, int BLOCK>
+struct SieveShCommon {
+  uint64_t tile[T + 1];
+  uint64_t hits[kHitCap];
+  uint32_t dres[kDenseMax], doff[kDenseMax], dq[kDenseMax], dp[kDenseMax], dpinv[kDenseMax], dprefix[kDenseMax];
+  uint8_t slot_d[kDenseSlotMax];
+  uint32_t hit_n, n_act, stage_n, pad;
+  uint32_t wsum[BLOCK / 64];
+};
+
+template <int T, int BLOCK>
+struct SieveShKeys : SieveShCommon<T, BLOCK> {
+  Entry stage[kStageCap];
+  uint16_t sb[kStageCap], rank[kStageCap], perm[kStageCap];
+  uint32_t hist[kB1Max], off[kB1Max], gbase[kB1Max];
+};
+
+template <int T, int BLOCK, int MODE>
+struct SieveShSel {
+  using type = SieveShCommon<T, BLOCK>;
+};
+template <int T, int BLOCK>
+struct SieveShSel<T, BLOCK, MODE_KEYS> {
+  using type = SieveShKeys<T, BLOCK>;
+};
+
+// Write the staged entries to their first-level buckets: counting sort by
+// bucket in LDS, one global reservation per non-empty bucket, then runs of
+// consecutive entries per bucket (coalesced 16 B stores).
+template <int T, int BLOCK>
+__device__ void flush_stage(SieveShKeys<T, BLOCK>& sh, const SieveParams& P) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  const uint32_t n = sh.stage_n;
+  const uint32_t B1 = P.b1mask + 1;
+  for (uint32_t b = tid; b < B1; b += BLOCK) sh.hist[b] = 0;
+  __syncthreads();
+  for (uint32_t i = tid; i < n; i += BLOCK) sh.rank[i] = static_cast<uint16_t>(atomicAdd(&sh.hist[sh.sb[i]], 1u));
+  __syncthreads();
+  static_assert(kB1Max <= BLOCK || BLOCK >= 1024, "one bucket per thread");
+  const uint32_t c = static_cast<uint32_t>(tid) < B1 ? sh.hist[tid] : 0u;
+  uint32_t tot;
+  const uint32_t ex = block_exclusive_scan<BLOCK>(c, sh.wsum, &tot);
+  if (static_cast<uint32_t>(tid) < B1) {
+    sh.off[tid] = ex;
+    sh.gbase[tid] = c ? atomicAdd(&P.cnt1[tid], c) : 0u;
+  }
+  __syncthreads();
+  for (uint32_t i = tid; i < n; i += BLOCK) sh.perm[sh.off[sh.sb[i]] + sh.rank[i]] = static_cast<uint16_t>(i);
+  __syncthreads();
+  for (uint32_t j = tid; j < n; j += BLOCK) {
+    const uint32_t i = sh.perm[j];
+    const uint32_t b = sh.sb[i];
+    const uint64_t k = static_cast<uint64_t>(sh.gbase[b]) + (j - sh.off[b]);
+    if (k < P.cap1)
+      P.l1[static_cast<uint64_t>(b) * P.cap1 + k] = sh.stage[i];
+    else
+      atomicOr(&P.flags[kFlagL1Overflow], 1u);
+  }
+  __syncthreads();
+  if (tid == 0) sh.stage_n = 0;
+  __syncthreads();
+}
+
+template <int T, int BLOCK, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
+  using Sh = typename SieveShSel<T, BLOCK, MODE>::type;
+  __shared__ Sh sh;
+  const int tid = threadIdx.x;
+  const DenseTab* D = P.dense;
+  const uint32_t nd = D->n, nslots = D->nslots;
+  for (uint32_t i = tid; i < nd; i += BLOCK) {
+    sh.dq[i] = D->q[i];
+    sh.dp[i] = D->p[i];
+    sh.dpinv[i] = D->pinv[i];
+    sh.dprefix[i] = D->prefix[i];
+  }
+  for (uint32_t i = tid; i < nslots; i += BLOCK) sh.slot_d[i] = D->slot_d[i];
+  if (tid == 0) sh.stage_n = 0;
+  __syncthreads();
+  uint64_t* spill = P.spill + static_cast<uint64_t>(blockIdx.x) * P.spill_cap;
+
+  for (uint64_t s = blockIdx.x; s < P.n_segs; s += gridDim.x) {
+    // Segment s -> query q and its x-interval [start, start + len).
+    uint32_t lo = 0, hi = P.n_queries;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (P.seg_prefix[mid] <= s)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const uint32_t qi = lo;
+    const uint64_t qa = P.queries[qi].a, qb = P.queries[qi].b;
+    const uint64_t start = qa + (s - P.seg_prefix[qi]) * static_cast<uint64_t>(P.seg_len);
+    const uint32_t len = static_cast<uint32_t>(min(static_cast<uint64_t>(P.seg_len), qb - start));
+    const uint64_t V = start + len;  // largest value sieved in this segment
+    if (tid == 0) {
+      uint32_t l = P.n_dense, h = P.n_pp;
+      while (l < h) {
+        const uint32_t m = (l + h) >> 1;
+        if (P.pp[m].q <= V)
+          l = m + 1;
+        else
+          h = m;
+      }
+      sh.n_act = l;
+      sh.hit_n = 0;
+    }
+    if (static_cast<uint32_t>(tid) < nd) sh.dres[tid] = static_cast<uint32_t>(start % sh.dq[tid]);
+    __syncthreads();
+
+    // Sparse prime powers (q > tile): at most one multiple per tile.  Their
+    // multiples in [start, V] are listed once per segment (Algorithm 1's
+    // first-multiple offset, start mod q).
+    const uint32_t n_act = sh.n_act;
+    for (uint32_t idx = P.n_dense + tid; idx < n_act; idx += BLOCK) {
+      const PrimePow pw = P.pp[idx];
+      const uint64_t r = mod_fp64(start, pw.q, pw.invq);
+      for (uint64_t j = r ? pw.q - r : 0; j <= len; j += pw.q) {
+        const uint32_t k = atomicAdd(&sh.hit_n, 1u);
+        const uint64_t e = (j << 32) | pw.p;
+        if (k < kHitCap)
+          sh.hits[k] = e;
+        else if (k - kHitCap < P.spill_cap)
+          spill[k - kHitCap] = e;
+        else
+          atomicOr(&P.flags[kFlagSpillOverflow], 1u);
+      }
+    }
+    __syncthreads();
+    const uint32_t nh = min(sh.hit_n, kHitCap + P.spill_cap);
+
+    for (uint32_t base = 0; base < len; base += T) {
+      const uint32_t cnt = min(static_cast<uint32_t>(T), len - base);
+      const uint64_t x0 = start + base;
+      // r[n] <- n with the prime 2 already reduced (count trailing zeros).
+      for (uint32_t i = tid; i <= cnt; i += BLOCK) sh.tile[i] = strip_two(x0 + i);
+      if (static_cast<uint32_t>(tid) < nd) {
+        const uint32_t qd = sh.dq[tid];
+        const uint32_t r = (sh.dres[tid] + base % qd) % qd;
+        sh.doff[tid] = r ? qd - r : 0u;
+      }
+      __syncthreads();
+      // Dense odd prime powers: divide r by p at every multiple of q = p^k.
+      for (uint32_t t = tid; t < nslots; t += BLOCK) {
+        const uint32_t d = sh.slot_d[t];
+        const uint32_t pos = sh.doff[d] + (t - sh.dprefix[d]) * sh.dq[d];
+        if (pos <= cnt) lds_div(&sh.tile[pos], sh.dp[d], sh.dpinv[d]);
+      }
+      // Sparse hits of this tile.
+      for (uint32_t h = tid; h < nh; h += BLOCK) {
+        const uint64_t e = h < kHitCap ? sh.hits[h] : spill[h - kHitCap];
+        const uint32_t pos = static_cast<uint32_t>(e >> 32);
+        if (pos >= base && pos <= base + cnt) {
+          const uint32_t p = static_cast<uint32_t>(e);
+          lds_div(&sh.tile[pos - base], p, inv32(p));
+        }
+      }
+      __syncthreads();
+
+      if constexpr (MODE == MODE_RAD) {
+        for (uint32_t i = tid; i < cnt; i += BLOCK) {
+          const uint64_t x = x0 + i;
+          if (x >= P.rad_lo && x < P.rad_hi) P.rad_out[x - P.rad_lo] = sh.tile[i];
+        }
+      } else {
+        if (sh.stage_n + cnt > static_cast<uint32_t>(kStageCap)) flush_stage<T, BLOCK>(sh, P);
+        const uint32_t grp = P.batch ? qi : 0u;
+        for (uint32_t i0 = 0; i0 < cnt; i0 += BLOCK) {
+          const uint32_t i = i0 + tid;
+          bool keep = false;
+          Entry en{0, 0};
+          uint32_t b1 = 0;
+          if (i < cnt) {
+            const uint64_t a = sh.tile[i], b = sh.tile[i + 1];
+            const uint64_t klo = a < b ? a : b, khi = a < b ? b : a;
+            const uint32_t h = key_hash(klo, khi, grp);
+            keep = !P.pfilter || (h >> P.pshift) == P.pval;
+            if (keep) {
+              b1 = (h >> P.b1shift) & P.b1mask;
+              const uint64_t x = x0 + i;
+              en = make_entry(klo, khi, P.batch ? x - qa : x, grp, a > b ? 1u : 0u);
+            }
+          }
+          const uint64_t mask = __ballot(keep);
+          const uint32_t nk = __popcll(mask);
+          const uint32_t lane = lane_id();
+          const uint32_t rk = __popcll(mask & ((1ull << lane) - 1ull));
+          uint32_t wb = 0;
+          if (lane == 0 && nk) wb = atomicAdd(&sh.stage_n, nk);
+          wb = __shfl(wb, 0, 64);
+          if (keep) {
+            sh.stage[wb + rk] = en;
+            sh.sb[wb + rk] = static_cast<uint16_t>(b1);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if constexpr (MODE == MODE_KEYS) {
+    __syncthreads();
+    if (sh.stage_n > 0) flush_stage<T, BLOCK>(sh, P);
+  }
+}
+
+struct PartParams {
+  const Entry* l1;
+  uint64_t cap1;
+  const uint32_t* cnt1;
+  uint32_t B1;
+  uint32_t chunks_per_bucket;
+  Entry* l2;
+  uint32_t cap2;
+  uint32_t* cnt2;
+  uint32_t b2shift, b2mask;
+  uint32_t gmask;
+  uint32_t* flags;
+};
+
+// Second scatter: one chunk of a first-level bucket per workgroup.  Workgroup
+// l runs on XCD l mod 8 (round-robin dispatch); the mapping keeps every chunk
+// of a bucket on one XCD so the partially written lines of its sub-buckets
+// stay in that XCD's L2 until they are complete.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
+  __shared__ Entry ent[kPartChunk];
+  __shared__ uint16_t sb[kPartChunk], rank[kPartChunk], perm[kPartChunk];
+  __shared__ uint32_t hist[kB2Max], off[kB2Max], gbase[kB2Max];
+  __shared__ uint32_t wsum[BLOCK / 64];
+  const int tid = threadIdx.x;
+  const uint32_t l = blockIdx.x;
+  const uint32_t xcd = l & 7u, slot = l >> 3;
+  const uint32_t jb = slot / P.chunks_per_bucket, chunk = slot % P.chunks_per_bucket;
+  const uint32_t b1 = jb * 8u + xcd;
+  if (b1 >= P.B1) return;
+  const uint64_t n1 = min(static_cast<uint64_t>(P.cnt1[b1]), P.cap1);
+  const uint64_t s0 = static_cast<uint64_t>(chunk) * kPartChunk;
+  if (s0 >= n1) return;
+  const uint32_t n = static_cast<uint32_t>(min(static_cast<uint64_t>(kPartChunk), n1 - s0));
+  const Entry* src = P.l1 + static_cast<uint64_t>(b1) * P.cap1 + s0;
+  const uint32_t B2 = P.b2mask + 1;
+  for (uint32_t b = tid; b < B2; b += BLOCK) hist[b] = 0;
+  for (uint32_t i = tid; i < n; i += BLOCK) {
+    const Entry e = src[i];
+    ent[i] = e;
+    const uint32_t h = key_hash(entry_lo(e), entry_hi(e), entry_grp(e, P.gmask));
+    sb[i] = static_cast<uint16_t>((h >> P.b2shift) & P.b2mask);
+  }
+  __syncthreads();
+  for (uint32_t i = tid; i < n; i += BLOCK) rank[i] = static_cast<uint16_t>(atomicAdd(&hist[sb[i]], 1u));
+  __syncthreads();
+  // Exclusive scan over B2 bins, BINS consecutive bins per thread.
+  constexpr int BINS = kB2Max / BLOCK;
+  uint32_t loc[BINS];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < BINS; ++k) {
+    const uint32_t b = tid * BINS + k;
+    loc[k] = b < B2 ? hist[b] : 0u;
+    sum += loc[k];
+  }
+  uint32_t tot;
+  uint32_t ex = block_exclusive_scan<BLOCK>(sum, wsum, &tot);
+#pragma unroll
+  for (int k = 0; k < BINS; ++k) {
+    const uint32_t b = tid * BINS + k;
+    if (b < B2) {
+      off[b] = ex;
+      gbase[b] = loc[k] ? atomicAdd(&P.cnt2[static_cast<uint64_t>(b1) * B2 + b], loc[k]) : 0u;
+    }
+    ex += loc[k];
+  }
+  __syncthreads();
+  for (uint32_t i = tid; i < n; i += BLOCK) perm[off[sb[i]] + rank[i]] = static_cast<uint16_t>(i);
+  __syncthreads();
+  for (uint32_t j = tid; j < n; j += BLOCK) {
+    const uint32_t i = perm[j];
+    const uint32_t b = sb[i];
+    const uint64_t k = static_cast<uint64_t>(gbase[b]) + (j - off[b]);
+    if (k < P.cap2)
+      P.l2[(static_cast<uint64_t>(b1) * B2 + b) * P.cap2 + k] = ent[i];
+    else
+      atomicOr(&P.flags[kFlagL2Overflow], 1u);
+  }
+}
+
+struct JoinParams {
+  const Entry* l2;
+  uint32_t cap2;
+  const uint32_t* cnt2;
+  uint64_t n_sub;
+  uint64_t kmask1;
+  uint32_t gmask;
+  Cand* cand;
+  uint32_t cand_cap;
+  uint32_t* flags;
+};
+
+__device__ __forceinline__ void emit_cand(const JoinParams& P, const Entry& a, const Entry& b) {
+  const uint32_t k = atomicAdd(&P.flags[kFlagCand], 1u);
+  if (k < P.cand_cap) {
+    Cand c;
+    c.a = a;
+    c.b = b;
+    P.cand[k] = c;
+  }
+}
+
+// LDS hash join of one second-level partition.  Each insert walks its probe
+// chain to the first empty slot and compares the key with every occupied slot
+// on the way (Algorithm 3's insert step).  Two equal keys follow the same
+// chain, so the one that claims the later slot passes the other and reports
+// the pair; every pair of a group is reported once.  Partitions larger than
+// one LDS chunk are joined chunk by chunk: after chunk c is inserted, every
+// later entry probes it (walking to an empty slot, as the probe step does).
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_join(JoinParams P) {
+  __shared__ Entry ent[kJoinCap];
+  __shared__ uint32_t table[kJoinSlots];
+  constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+  const int tid = threadIdx.x;
+  const uint64_t sbk = blockIdx.x;
+  if (sbk >= P.n_sub) return;
+  const uint32_t n = min(P.cnt2[sbk], P.cap2);
+  if (n < 2) return;
+  const Entry* src = P.l2 + sbk * P.cap2;
+  for (uint32_t i0 = 0; i0 < n; i0 += kJoinCap) {
+    const uint32_t m = min(static_cast<uint32_t>(kJoinCap), n - i0);
+    for (uint32_t s = tid; s < static_cast<uint32_t>(kJoinSlots); s += BLOCK) table[s] = kEmpty;
+    for (uint32_t i = tid; i < m; i += BLOCK) ent[i] = src[i0 + i];
+    __syncthreads();
+    for (uint32_t i = tid; i < m; i += BLOCK) {
+      const Entry e = ent[i];
+      const uint64_t k0 = e.w0 & kM42, k1 = e.w1 & P.kmask1;
+      const uint32_t h = key_hash2(k0, e.w1 & kM42, entry_grp(e, P.gmask));
+      const uint32_t mine = (h & 0xFFFF0000u) | i;
+      uint32_t s = h & (kJoinSlots - 1);
+      for (;;) {
+        uint32_t v = table[s];
+        if (v == kEmpty) {
+          v = atomicCAS(&table[s], kEmpty, mine);
+          if (v == kEmpty) break;
+        }
+        if (((v ^ mine) >> 16) == 0) {
+          const Entry f = ent[v & 0xFFFFu];
+          if ((f.w0 & kM42) == k0 && (f.w1 & P.kmask1) == k1) emit_cand(P, e, f);
+        }
+        s = (s + 1) & (kJoinSlots - 1);
+      }
+    }
+    __syncthreads();
+    for (uint32_t jj = i0 + m + tid; jj < n; jj += BLOCK) {
+      const Entry e = src[jj];
+      const uint64_t k0 = e.w0 & kM42, k1 = e.w1 & P.kmask1;
+      const uint32_t h = key_hash2(k0, e.w1 & kM42, entry_grp(e, P.gmask));
+      uint32_t s = h & (kJoinSlots - 1);
+      for (;;) {
+        const uint32_t v = table[s];
+        if (v == kEmpty) break;
+        if (((v ^ h) >> 16) == 0) {
+          const Entry f = ent[v & 0xFFFFu];
+          if ((f.w0 & kM42) == k0 && (f.w1 & P.kmask1) == k1) emit_cand(P, e, f);
+        }
+        s = (s + 1) & (kJoinSlots - 1);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+struct VerifyParams {
+  const Cand* cand;
+  uint32_t n_cand;
+  const uint32_t* primes;  // all primes <= sqrt(hi_max), ascending
+  uint32_t n_primes;
+  const Query* queries;
+  int batch;
+  uint32_t kinds;
+  OutPair* out;
+  uint32_t out_cap;
+  uint32_t* flags;
+};
+
+// One workgroup per candidate pair: rad of m, m+1, n, n+1 by trial division
+// (the definition of the radical), with the cofactor left after dividing out
+// every prime <= sqrt(v) being 1 or one more prime.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_verify(VerifyParams P) {
+  __shared__ uint64_t red_r[4][BLOCK], red_s[4][BLOCK];
+  const int tid = threadIdx.x;
+  const uint32_t c = blockIdx.x;
+  if (c >= P.n_cand) return;
+  const Cand cd = P.cand[c];
+  const uint32_t qa_idx = entry_grp(cd.a, P.batch ? kGrpMask : 0u);
+  const uint64_t off = P.batch ? P.queries[qa_idx].a : 0ull;
+  const uint64_t xa = entry_pos(cd.a, P.batch) + off, xb = entry_pos(cd.b, P.batch) + off;
+  const uint64_t m = xa < xb ? xa : xb, n = xa < xb ? xb : xa;
+  const uint64_t v[4] = {m, m + 1, n, n + 1};
+  uint64_t pr[4] = {1, 1, 1, 1}, sm[4] = {1, 1, 1, 1};
+  for (uint32_t i = tid; i < P.n_primes; i += BLOCK) {
+    const uint64_t p = P.primes[i];
+    if (p * p > n + 1) break;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (p * p <= v[k] && v[k] % p == 0) {
+        pr[k] *= p;
+        uint64_t t = v[k], pk = 1;
+        while (t % p == 0) {
+          t /= p;
+          pk *= p;
+        }
+        sm[k] *= pk;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    red_r[k][tid] = pr[k];
+    red_s[k][tid] = sm[k];
+  }
+  __syncthreads();
+  for (int w = BLOCK / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        red_r[k][tid] *= red_r[k][tid + w];
+        red_s[k][tid] *= red_s[k][tid + w];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    uint64_t rad[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint64_t cof = v[k] / red_s[k][0];
+      rad[k] = red_r[k][0] * (cof > 1 ? cof : 1);
+    }
+    const uint64_t lo_m = rad[0] < rad[1] ? rad[0] : rad[1], hi_m = rad[0] < rad[1] ? rad[1] : rad[0];
+    const uint64_t lo_n = rad[2] < rad[3] ? rad[2] : rad[3], hi_n = rad[2] < rad[3] ? rad[3] : rad[2];
+    const bool same = (lo_m == lo_n) && (hi_m == hi_n) && m != n;
+    const bool matches_key = lo_m == entry_lo(cd.a) && hi_m == entry_hi(cd.a);
+    if (!same || !matches_key) {
+      atomicAdd(&P.flags[kFlagVerifyFail], 1u);
+    } else {
+      const uint32_t kind = rad[0] == rad[2] ? 1u : 2u;
+      if (P.kinds & kind) {
+        const uint32_t k = atomicAdd(&P.flags[kFlagOut], 1u);
+        if (k < P.out_cap) {
+          OutPair o;
+          o.m = m;
+          o.n = n;
+          o.kind = kind;
+          o.query = P.batch ? qa_idx : 0u;
+          P.out[k] = o;
+        }
+      }
+    }
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+}  // namespace bx

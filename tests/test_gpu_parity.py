@@ -1,0 +1,292 @@
+"""GPU parity: the HIP path (through the C-ABI) against the oracle and the paper's pins.
+
+Radicals are compared element by element with trial division; pair lists are
+compared bit-exactly as sorted lists.  Full-size cases compare the pair list with
+Theorem 1 (complete up to 1.4e12) and radicals sampled one by one.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_facts import theorem1_pairs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2506_01099_amd import Benelux
+
+    c = Benelux(device=0)
+    yield c
+    c.close()
+
+
+def squarefree_count(n):
+    r = math.isqrt(n)
+    mu = np.ones(r + 1, dtype=np.int64)
+    comp = np.zeros(r + 1, dtype=bool)
+    for p in range(2, r + 1):
+        if not comp[p]:
+            comp[2 * p::p] = True
+            mu[p::p] *= -1
+            mu[p * p::p * p] = 0
+    return int(sum(int(mu[d]) * (n // (d * d)) for d in range(1, r + 1)))
+
+
+# --- radicals -----------------------------------------------------------------------
+
+@pytest.mark.parametrize("lo,hi", [
+    (1, 2), (1, 3), (5, 5), (1, 4097), (1, 4098), (1, (1 << 16) + 3), (1, (1 << 17) + 1),
+    ((1 << 17) - 7, (1 << 17) + 9), ((1 << 20) - 100, (1 << 20) + 300),
+    ((1 << 32) - 3000, (1 << 32) + 1000),
+    ((1 << 36) - 70000, (1 << 36) + 70000),  # crosses a segment boundary (segments of 2^17)
+    ((1 << 40) - 5000, (1 << 40) + 5000),
+    ((1 << 42) - 20001, (1 << 42) - 1),
+])
+def test_radicals_match_oracle(ctx, lo, hi):
+    say(f"radicals [{lo}, {hi})")
+    got = ctx.radical_segment(lo, hi)
+    want = oracle.radicals(lo, hi) if hi > lo else np.empty(0, dtype=np.uint64)
+    assert got.dtype == np.uint64 and got.size == hi - lo
+    assert np.array_equal(got, want)
+
+
+def test_radicals_special_values(ctx):
+    """Prime powers near the top of the table, 3^26, 2^41, p^2 for the largest table prime."""
+    lim = math.isqrt((1 << 42) - 1)
+    p = lim
+    while any(p % d == 0 for d in range(2, math.isqrt(p) + 1)):
+        p -= 1
+    for v in [p * p, 3**26, 2**41, 5**17, 7**14, 2**41 - 1, p * (p - 2)]:
+        lo = max(1, v - 300)
+        hi = min((1 << 42) - 1, v + 300)
+        say(f"radicals around {v}")
+        got = ctx.radical_segment(lo, hi)
+        assert np.array_equal(got, oracle.radicals(lo, hi)), v
+
+
+def test_radicals_squarefree_count_2_24(ctx):
+    N = 1 << 24
+    r = ctx.radical_segment(1, N + 1)
+    x = np.arange(1, N + 1, dtype=np.uint64)
+    assert int(np.count_nonzero(r == x)) == squarefree_count(N)
+
+
+def test_radicals_squarefree_count_2_30_on_device(ctx):
+    """Aggregate pin at a size trial division cannot reach: #{x <= N : rad(x) = x} (Moebius)."""
+    import torch
+
+    N = 1 << 30
+    chunk = 1 << 27
+    count = 0
+    buf = torch.empty(chunk, dtype=torch.int64, device="cuda")
+    for lo in range(1, N + 1, chunk):
+        hi = min(N + 1, lo + chunk)
+        ctx.radical_segment_dev(lo, hi, buf)
+        xs = torch.arange(lo, hi, dtype=torch.int64, device="cuda")
+        count += int((buf[: hi - lo] == xs).sum().item())
+    assert count == squarefree_count(N)
+
+
+def test_radicals_sampled_at_scale(ctx):
+    rng = np.random.default_rng(36)
+    for mag in (32, 36, 40, 41):
+        xs = rng.integers(1 << (mag - 1), 1 << mag, size=12)
+        for x in xs:
+            x = int(x)
+            got = ctx.radical_segment(x, x + 2)
+            assert [int(v) for v in got] == [oracle.rad(x), oracle.rad(x + 1)], x
+
+
+def test_radical_segment_dev_matches_host(ctx):
+    import torch
+
+    lo, hi = (1 << 33) + 17, (1 << 33) + 17 + 300000
+    t = torch.empty(hi - lo, dtype=torch.int64, device="cuda")
+    ctx.radical_segment_dev(lo, hi, t)
+    torch.cuda.synchronize()
+    assert np.array_equal(t.cpu().numpy().astype(np.uint64), ctx.radical_segment(lo, hi))
+
+
+# --- searches -------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N", [1, 2, 3, 8, 100, 1215, 4096, 4374, 1 << 16, 1 << 20])
+def test_search_matches_oracle(ctx, N):
+    say(f"search N={N}")
+    assert ctx.search(N) == oracle.search(N)
+
+
+def test_search_2_24_matches_oracle(ctx):
+    N = 1 << 24
+    got = ctx.search(N)
+    assert got == oracle.search(N)
+    st = ctx.stats()
+    assert st["entries"] == N and st["integers"] == N
+
+
+@pytest.mark.parametrize("a,b", [(1, 9), (2, 9), (3, 9), (35, 4375), (36, 4375), (35, 4374), (126, 16129),
+                                 (127, 16129), (1000, (1 << 20) + 1), (70, 1300), ((1 << 20) - 5, (1 << 20) + 5)])
+def test_search_range_matches_oracle(ctx, a, b):
+    assert ctx.search_range(a, b) == oracle.search_range(a, b)
+
+
+@pytest.mark.parametrize("kinds", [1, 2, 3])
+def test_kinds_filter(ctx, kinds):
+    assert ctx.search(1 << 20, kinds) == oracle.search(1 << 20, kinds)
+
+
+@pytest.mark.parametrize("passes", [1, 2, 4, 16, 64])
+def test_pass_count_invariance(ctx, passes):
+    ctx.set_option("passes", passes)
+    try:
+        got = ctx.search(1 << 20)
+        st = ctx.stats()
+    finally:
+        ctx.set_option("passes", 0)
+    assert got == oracle.search(1 << 20)
+    assert st["passes"] >= passes and st["entries"] == 1 << 20
+
+
+@pytest.mark.parametrize("b1,b2", [(1, 1), (2, 3), (10, 1), (3, 12)])
+def test_partition_shape_invariance(ctx, b1, b2):
+    """Large partitions take the chunked LDS join; many small ones the single-chunk path."""
+    ctx.set_option("b1_bits", b1)
+    ctx.set_option("b2_bits", b2)
+    try:
+        got = ctx.search(1 << 18)
+    finally:
+        ctx.set_option("b1_bits", 0)
+        ctx.set_option("b2_bits", 0)
+    assert got == oracle.search(1 << 18)
+
+
+@pytest.mark.parametrize("seg", [4096, 8192, 1 << 17, 1 << 20])
+def test_segment_length_invariance(ctx, seg):
+    ctx.set_option("seg_len", seg)
+    try:
+        got = ctx.search(1 << 20)
+        rad = ctx.radical_segment((1 << 36) - 9000, (1 << 36) + 9000)
+    finally:
+        ctx.set_option("seg_len", 0)
+    assert got == oracle.search(1 << 20)
+    assert np.array_equal(rad, oracle.radicals((1 << 36) - 9000, (1 << 36) + 9000))
+
+
+def test_repeat_determinism(ctx):
+    a = ctx.search(1 << 22)
+    b = ctx.search(1 << 22)
+    assert a == b == theorem1_pairs(1 << 22)
+
+
+def test_invariant_larger_member_non_squarefree(ctx):
+    for m, n, _ in ctx.search(1 << 26):
+        if (m, n) == (2, 3):
+            continue
+        r = ctx.radical_segment(n, n + 2)
+        assert int(r[0]) < n and int(r[1]) < n + 1
+
+
+# --- full sizes -----------------------------------------------------------------------
+
+def test_search_2_28_theorem1(ctx):
+    got = ctx.search(1 << 28)
+    assert got == theorem1_pairs(1 << 28)
+    assert len(got) == 29
+
+
+def test_search_2_32_theorem1(ctx):
+    say("search N=2^32 (one pass)")
+    got = ctx.search(1 << 32)
+    st = ctx.stats()
+    assert got == theorem1_pairs(1 << 32)
+    assert len(got) == 33
+    assert st["entries"] == 1 << 32
+
+
+def test_search_2_36_theorem1(ctx):
+    say("search N=2^36 (hash-partitioned passes)")
+    got = ctx.search(1 << 36)
+    st = ctx.stats()
+    assert got == theorem1_pairs(1 << 36)
+    assert len(got) == 37
+    assert st["entries"] == 1 << 36 and st["passes"] >= 16
+
+
+# --- batched --------------------------------------------------------------------------
+
+def test_batch_planted_matches_oracle(ctx):
+    from paper_2506_01099_amd.inputs import planted_queries
+
+    a, b = planted_queries()
+    got = ctx.search_batch(a, b)
+    for i in range(a.size):
+        assert got[i] == oracle.search_range(int(a[i]), int(b[i])), (int(a[i]), int(b[i]))
+
+
+def test_batch_random_matches_oracle_and_sequential(ctx):
+    from paper_2506_01099_amd.inputs import batched_queries
+
+    a, b = batched_queries(n=48, seed=7, log2_min=8, log2_max=12, a_bits=34)
+    got = ctx.search_batch(a, b)
+    for i in range(a.size):
+        want = oracle.search_range(int(a[i]), int(b[i]))
+        assert got[i] == want
+        assert ctx.search_range(int(a[i]), int(b[i])) == want
+
+
+def test_batch_overlapping_and_degenerate_queries(ctx):
+    a = np.array([1, 1, 2, 5, 5, 100, 0, 3], dtype=np.uint64)
+    b = np.array([5000, 5000, 9, 5, 6, 100, 10, 2], dtype=np.uint64)
+    got = ctx.search_batch(a, b)
+    for i in range(a.size):
+        assert got[i] == oracle.search_range(int(a[i]), int(b[i]) if b[i] >= a[i] else int(a[i]))
+
+
+def test_batch_config_queries_sampled(ctx):
+    """The 4096 seeded queries of the batched workload; a sample is re-run one by one."""
+    from paper_2506_01099_amd.inputs import batched_queries
+
+    a, b = batched_queries()
+    got = ctx.search_batch(a, b)
+    for i in range(0, 4096, 256):
+        assert got[i] == ctx.search_range(int(a[i]), int(b[i]))
+    small = [i for i in range(4096) if int(b[i] - a[i]) <= 2048][:8]
+    for i in small:
+        assert got[i] == oracle.search_range(int(a[i]), int(b[i]))
+
+
+# --- served ---------------------------------------------------------------------------
+
+def test_served_alone_equals_in_mix(ctx):
+    import time
+
+    from paper_2506_01099_amd import Server
+
+    reqs = [(1, 1 << 20), (2, 9), (70, 1300), (1 << 30, (1 << 30) + (1 << 22)), (30, 100000), (1, 1 << 16)]
+    alone = [ctx.search_range(a, b) for a, b in reqs]
+    srv = Server(ctx, budget_bytes=8 << 30, max_inflight=2)
+    try:
+        tickets = [srv.submit(a, b) for a, b in reqs]
+        deadline = time.time() + 60
+        results = {}
+        while len(results) < len(tickets) and time.time() < deadline:
+            for t in tickets:
+                if t not in results and srv.poll(t):
+                    results[t] = srv.take(t)
+            time.sleep(0.001)
+    finally:
+        srv.stop()
+    assert len(results) == len(tickets)
+    for t, want in zip(tickets, alone):
+        pairs, ts, td = results[t]
+        assert pairs == want
+        assert td >= ts
