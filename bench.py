@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Benchmark of the Benelux-pair search on one MI355X.
+
+A step is one whole search: radicals sieved for every x of the workload, keys
+generated, the hash-partitioned exact join over all passes, verification and the
+sorted pair list.  The headline workload is the plain search up to N = 2^36, both
+kinds.  Prints ONE JSON line (rank 0, N = 1 GPU).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--log2n 36]
+                  [--batched] [--served SECONDS] [--no-cpu]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+VALU_PEAK_INT_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes/clk x 2.4 GHz (32-bit integer lane-ops/s)
+# Algorithmic 32-bit integer ops per sieved integer (derivation in the design doc: strip the
+# factor 2, the odd prime-power divisions at 0.273 per integer, canonical key, hash, pass test).
+SIEVE_OPS_PER_INT = 27.0
+ENTRY_BYTES = 16
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--log2n", type=int, default=36)
+    ap.add_argument("--batched", action="store_true", help="also time the 4096-query batched workload")
+    ap.add_argument("--served", type=float, default=0.0, help="also run the served trace for this many seconds")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-sample-log2", type=int, default=22)
+    return ap.parse_args()
+
+
+def cpu_baseline(N, log2_sample):
+    import oracle
+
+    S = 1 << log2_sample
+    a = max(1, N - S)
+    threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    pairs, t_rad, t_join = oracle.search_range_timed(a, N + 1, 3, threads)
+    dt = time.perf_counter() - t0
+    return {"value": (N + 1 - a) / dt, "unit": "integers/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle.search_range over x in [{a}, {N + 1}) ({N + 1 - a} integers at magnitude 2^{int(math.log2(N))}); "
+                      f"radicals {t_rad:.2f} s on {threads} threads, hash-map join {t_join:.2f} s on 1 thread",
+            "seconds": dt}
+
+
+def run_plain(bx, N, steps, warmup):
+    for i in range(warmup):
+        log(f"warmup {i + 1}/{warmup}: search N=2^{int(math.log2(N))}")
+        bx.search(N)
+    import torch
+
+    torch.cuda.synchronize()
+    per_step = []
+    agg = None
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ts = time.perf_counter()
+        pairs = bx.search(N)
+        st = bx.stats()
+        per_step.append(time.perf_counter() - ts)
+        log(f"step {i + 1}/{steps}: {per_step[-1]:.3f} s, {len(pairs)} pairs, kernel ms {st['kernel_ms']}")
+        if agg is None:
+            agg = {k: dict(v) if isinstance(v, dict) else v for k, v in st.items()}
+        else:
+            for k in ("sieve", "partition", "join", "verify"):
+                agg["kernel_ms"][k] += st["kernel_ms"][k]
+                agg["launches"][k] += st["launches"][k]
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    return pairs, total, per_step, agg
+
+
+def roofline_from(agg, n_keys_per_step, steps):
+    ms = agg["kernel_ms"]
+    ln = agg["launches"]
+    kinds = {k: ms[k] for k in ("sieve", "partition", "join")}
+    dominant = max(kinds, key=kinds.get)
+    out = {}
+    # Sieve: ALU-bound.  Algorithmic ops per launch = ops per integer x integers per launch.
+    if ln["sieve"]:
+        avg_ms = ms["sieve"] / ln["sieve"]
+        ints_per_launch = n_keys_per_step * steps / ln["sieve"]
+        ach = SIEVE_OPS_PER_INT * ints_per_launch / (avg_ms * 1e-3) / 1e12
+        out["sieve"] = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_INT_OPS / 1e12, "unit": "Tops/s",
+                        "frac": ach / (VALU_PEAK_INT_OPS / 1e12), "traffic": None,
+                        "avg_launch_ms": avg_ms, "integers_per_launch": ints_per_launch}
+    # Partition: HBM-bound, 16 B read + 16 B write per entry.
+    entries_per_step = n_keys_per_step
+    if ln["partition"]:
+        avg_ms = ms["partition"] / ln["partition"]
+        b = 2 * ENTRY_BYTES * entries_per_step * steps / ln["partition"]
+        ach = b / (avg_ms * 1e-3) / 1e9
+        out["partition"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": avg_ms,
+                            "bytes_per_launch": b}
+    if ln["join"]:
+        avg_ms = ms["join"] / ln["join"]
+        b = ENTRY_BYTES * entries_per_step * steps / ln["join"]
+        ach = b / (avg_ms * 1e-3) / 1e9
+        out["join"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": avg_ms,
+                       "bytes_per_launch": b}
+    # The join as a whole (second scatter + LDS join): 32 B per key algorithmic
+    # (one 16 B entry written by the sieve, read once), over the join kernels' time.
+    if ln["partition"] and ln["join"]:
+        t = (ms["partition"] + ms["join"]) * 1e-3
+        ach = 2 * ENTRY_BYTES * entries_per_step * steps / t / 1e9
+        out["join_total"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": ach / HBM_PEAK_GBS}
+    return dominant, out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described "
+              "in DESIGN.md and is not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2506_01099_amd import Benelux
+
+    N = 1 << args.log2n
+    bx = Benelux(device=0)
+    pairs, total, per_step, agg = run_plain(bx, N, args.steps, args.warmup)
+    ms_step = total / args.steps * 1e3
+    value = N / (total / args.steps)
+    dominant, roof = roofline_from(agg, N, args.steps)
+    line = {
+        "metric": "integers sieved+joined/s at N=2^36 (both kinds), %HBM roofline; batched vs plain",
+        "value": value,
+        "unit": "integers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic: the integers 1..N themselves (no dataset)",
+        "config": {"workload": f"plain search N=2^{args.log2n}, both kinds, hash-partitioned passes",
+                   "N": N, "passes": agg["passes"], "b1_bits": agg["b1_bits"], "b2_bits": agg["b2_bits"],
+                   "seg_len": agg["seg_len"], "tile": agg["tile"], "parallelism": "single GPU"},
+        "pairs_found": len(pairs),
+        "roofline": dict(roof[dominant], kernel=dominant),
+        "roofline_kernels": roof,
+        "kernel_ms_per_step": {k: v / args.steps for k, v in agg["kernel_ms"].items()},
+        "step_seconds": per_step,
+    }
+    if args.batched:
+        line["batched"] = run_batched(bx)
+    if args.served > 0:
+        line["served"] = run_served(bx, args.served)
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline(N, args.cpu_sample_log2)
+    bx.close()
+    print(json.dumps(line), flush=True)
+
+
+def run_batched(bx):
+    import numpy as np
+
+    from paper_2506_01099_amd.inputs import batched_queries
+
+    a, b = batched_queries()
+    total_L = int((b - a).sum())
+    bx.search_batch(a, b)  # warm
+    t0 = time.perf_counter()
+    res = bx.search_batch(a, b)
+    t_batch = time.perf_counter() - t0
+    st = bx.stats()
+    # plain single range of the same total length at offset 2^40
+    lo = 1 << 40
+    t0 = time.perf_counter()
+    bx.search_range(lo, lo + total_L)
+    t_plain = time.perf_counter() - t0
+    # a sample of the queries one by one through the plain range path
+    idx = np.arange(0, a.size, 16)
+    t0 = time.perf_counter()
+    for i in idx:
+        bx.search_range(int(a[i]), int(b[i]))
+    t_seq_sample = time.perf_counter() - t0
+    L_sample = int((b[idx] - a[idx]).sum())
+    return {"queries": int(a.size), "integers": total_L, "seconds": t_batch,
+            "integers_per_s": total_L / t_batch, "pairs": int(sum(len(r) for r in res)),
+            "plain_contiguous_integers_per_s": total_L / t_plain,
+            "one_by_one_integers_per_s": L_sample / t_seq_sample, "one_by_one_sample_queries": int(idx.size),
+            "kernel_ms": st["kernel_ms"], "passes": st["passes"]}
+
+
+def run_served(bx, seconds):
+    import numpy as np
+
+    from paper_2506_01099_amd import Server
+    from paper_2506_01099_amd.inputs import served_trace
+
+    t, a, b = served_trace(n=12000)
+    keep = t < seconds
+    t, a, b = t[keep], a[keep], b[keep]
+    srv = Server(bx, budget_bytes=200 << 30, max_inflight=2)
+    tickets = []
+    t_start = srv.now()
+    i = 0
+    done = {}
+    while len(done) < t.size:
+        now = srv.now() - t_start
+        while i < t.size and t[i] <= now:
+            tickets.append((srv.submit(int(a[i]), int(b[i])), t_start + t[i]))
+            i += 1
+        for tk, arr in tickets:
+            if tk not in done and srv.poll(tk):
+                pairs, ts, td = srv.take(tk)
+                done[tk] = (td - arr, len(pairs))
+        time.sleep(0.0005)
+    t_end = srv.now()
+    srv.stop()
+    lat = np.array([v[0] for v in done.values()])
+    total_L = int((b - a).sum())
+    return {"requests": int(t.size), "integers": total_L, "wall_s": t_end - t_start,
+            "integers_per_s": total_L / (t_end - t_start), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "pairs": int(sum(v[1] for v in done.values()))}
+
+
+if __name__ == "__main__":
+    main()

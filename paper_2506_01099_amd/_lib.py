@@ -50,6 +50,15 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
+    # Share one HIP runtime with PyTorch: torch bundles its own libamdhip64 /
+    # libhsa-runtime64 (same sonames).  Loading torch first makes the dynamic
+    # linker bind this library to those copies, so torch's device buffers and
+    # streams are valid handles for the library (two runtimes in one process
+    # cannot share a device).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2506_01099_amd.build.build() "
                           "(the HIP library is required; there is no fallback)")
