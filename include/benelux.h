@@ -137,12 +137,13 @@ typedef struct {
 int bx_get_stats(bx_ctx* ctx, bx_stats* out);
 
 /* Options (name = value); unknown names are BX_EINVAL.
- *   "passes"       force the number of hash passes (power of two, 0 = plan)
+ *   "passes"       force the number of hash passes (any count, 0 = plan)
  *   "seg_len"      sieve segment length (multiple of the tile, 0 = default)
  *   "timing"       1 = record HIP events per kernel (default 1)
  *   "verify"       1 = recompute every candidate by trial division (default 1)
  *   "b1_bits"      force the first partition fan-out (0 = plan)
- *   "b2_bits"      force the second partition fan-out (0 = plan)               */
+ *   "b2_bits"      force the second partition fan-out (0 = plan)
+ *   "group"        first-level buckets per second-level launch (1, 2, 4, 8; 0 = 8) */
 int bx_set_option(bx_ctx* ctx, const char* name, int64_t value);
 
 void bx_free(void* p);

@@ -76,7 +76,7 @@ struct DevBuf {
 };
 
 struct Plan {
-  uint32_t pbits = 0, b1bits = 0, b2bits = 0;
+  uint32_t passes = 1, b1bits = 0, b2bits = 0, group = 1;
   uint64_t cap1 = 0;
   uint32_t cap2 = 0;
   uint64_t bytes = 0;
@@ -102,7 +102,7 @@ struct bx_ctx {
   PrimePow* d_pp = nullptr;
   DenseTab* d_dense = nullptr;
   DevBuf l1, l2, cnt1, cnt2, cand, out, flags, spill, queries, segpref, rad;
-  int force_passes = 0, timing = 1, verify = 1, force_b1 = -1, force_b2 = -1;
+  int force_passes = 0, timing = 1, verify = 1, force_b1 = -1, force_b2 = -1, force_group = 0;
   uint32_t seg_len = kDefaultSegLen;
   bx_stats stats{};
   std::mutex mu;
@@ -288,43 +288,47 @@ uint64_t fixed_bytes(const bx_ctx* c, uint32_t sieve_grid) {
          (64ull << 20);
 }
 
-// Choose the number of hash passes P = 2^pbits and the two partition fan-outs
-// so that one pass's entries (16 B each, in both partition buffers) fit the
-// budget; partitions end up near 2048 entries, which one workgroup joins in LDS.
+// Choose the number of hash passes P (any integer: pass p keeps the keys whose
+// pass hash falls in the p-th of P equal ranges) and the two partition
+// fan-outs.  One pass's entries live in the first-level buckets (16 B each);
+// the second level only needs a buffer for one group of buckets at a time, so
+// the budget sets P through the first level alone.  Second-level partitions
+// end up near 1600-2400 entries, which one workgroup joins in LDS.
 int make_plan(bx_ctx* c, uint64_t n_keys, uint32_t sieve_grid, Plan* out) {
   const uint64_t fixed = fixed_bytes(c, sieve_grid);
-  for (uint32_t pbits = 0; pbits <= 16; ++pbits) {
-    if (c->force_passes > 0) {
-      pbits = ceil_log2(static_cast<double>(c->force_passes));
-    }
+  const uint32_t p_first = c->force_passes > 0 ? static_cast<uint32_t>(c->force_passes) : 1;
+  const uint32_t p_last = c->force_passes > 0 ? p_first : 4096;
+  for (uint32_t P = p_first; P <= p_last; ++P) {
     Plan p;
-    p.pbits = pbits;
-    const double n_pass = std::max(1.0, std::ceil(static_cast<double>(n_keys) / std::ldexp(1.0, static_cast<int>(pbits))));
-    const uint32_t total = n_pass > 2048.0 ? ceil_log2(n_pass / 2048.0) : 0;
-    uint32_t b1 = std::min<uint32_t>(10, total);
-    uint32_t b2 = total - b1;
+    p.passes = P;
+    const double n_pass = std::max(1.0, std::ceil(static_cast<double>(n_keys) / P));
+    uint32_t b1 = n_pass > 16384.0 ? std::min<uint32_t>(10, ceil_log2(n_pass / 16384.0)) : 0;
     if (c->force_b1 >= 0) b1 = static_cast<uint32_t>(c->force_b1);
+    p.b1bits = b1;
+    p.cap1 = round_up(static_cast<uint64_t>(std::ceil(n_pass / std::ldexp(1.0, static_cast<int>(b1)) * 1.03)) + 2048, 64);
+    uint32_t b2 = p.cap1 > 2400 ? ceil_log2(static_cast<double>(p.cap1) / 2400.0) : 0;
     if (c->force_b2 >= 0) b2 = static_cast<uint32_t>(c->force_b2);
-    if (b1 > 10 || b2 > 12 || pbits + b1 + b2 > 31) {
+    if (b2 > 13 || b1 + b2 > 32) {
       if (c->force_passes > 0) return fail(BX_ENOMEM, "forced pass count leaves partitions too large");
       continue;
     }
-    p.b1bits = b1;
     p.b2bits = b2;
-    p.cap1 = round_up(static_cast<uint64_t>(std::ceil(n_pass / std::ldexp(1.0, static_cast<int>(b1)) * 1.03)) + 2048, 64);
     p.cap2 = static_cast<uint32_t>(
         round_up(static_cast<uint64_t>(std::ceil(static_cast<double>(p.cap1) / std::ldexp(1.0, static_cast<int>(b2)) * 1.25)) + 64,
                  16));
     if (p.cap1 > 0xF0000000ull) continue;
-    const uint64_t nb1 = 1ull << b1, nsub = 1ull << (b1 + b2);
-    p.bytes = nb1 * p.cap1 * sizeof(Entry) + nsub * p.cap2 * sizeof(Entry) + (nb1 + nsub) * 4;
-    if (p.bytes + fixed <= c->budget || c->force_passes > 0) {
-      if (p.bytes + fixed > c->budget)
-        return fail(BX_ENOMEM, "forced pass count needs " + std::to_string(p.bytes + fixed) + " bytes, budget " +
-                                   std::to_string(c->budget));
+    const uint64_t nb1 = 1ull << b1, nb2 = 1ull << b2;
+    uint32_t G = c->force_group > 0 ? static_cast<uint32_t>(c->force_group) : 8u;
+    if (G > nb1) G = static_cast<uint32_t>(nb1);
+    p.group = G;
+    p.bytes = nb1 * p.cap1 * sizeof(Entry) + G * nb2 * p.cap2 * sizeof(Entry) + (nb1 + G * nb2) * 4;
+    if (p.bytes + fixed <= c->budget) {
       *out = p;
       return BX_OK;
     }
+    if (c->force_passes > 0)
+      return fail(BX_ENOMEM, "forced pass count needs " + std::to_string(p.bytes + fixed) + " bytes, budget " +
+                                 std::to_string(c->budget));
   }
   return fail(BX_ENOMEM, "HBM budget too small for the search");
 }
@@ -401,18 +405,20 @@ int run_search(bx_ctx* c, Segs& s, int batch, uint32_t kinds, std::vector<OutPai
   const uint32_t sieve_grid = static_cast<uint32_t>(std::min<uint64_t>(s.n_segs, static_cast<uint64_t>(c->n_cu)));
   Plan plan;
   if ((rc = make_plan(c, s.n_keys, sieve_grid, &plan)) != BX_OK) return rc;
-  const uint32_t B1 = 1u << plan.b1bits, B2 = 1u << plan.b2bits;
-  const uint64_t nsub = static_cast<uint64_t>(B1) * B2;
+  const uint32_t B1 = 1u << plan.b1bits, B2 = 1u << plan.b2bits, G = plan.group;
+  const uint64_t ngsub = static_cast<uint64_t>(G) * B2;  // sub-buckets of one group
   if ((rc = ensure(c, c->l1, B1 * plan.cap1 * sizeof(Entry))) != BX_OK) return rc;
-  if ((rc = ensure(c, c->l2, nsub * plan.cap2 * sizeof(Entry))) != BX_OK) return rc;
+  if ((rc = ensure(c, c->l2, ngsub * plan.cap2 * sizeof(Entry))) != BX_OK) return rc;
   if ((rc = ensure(c, c->cnt1, B1 * 4ull)) != BX_OK) return rc;
-  if ((rc = ensure(c, c->cnt2, nsub * 4ull)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->cnt2, ngsub * 4ull)) != BX_OK) return rc;
   if ((rc = ensure(c, c->cand, kCandCap * sizeof(Cand))) != BX_OK) return rc;
   if ((rc = ensure(c, c->out, kCandCap * sizeof(OutPair))) != BX_OK) return rc;
   if ((rc = ensure(c, c->flags, kFlagCount * 4)) != BX_OK) return rc;
   if ((rc = ensure(c, c->spill, static_cast<size_t>(sieve_grid) * spill_cap_of(c) * 8)) != BX_OK) return rc;
   if ((rc = upload_segs(c, s, st)) != BX_OK) return rc;
   if ((rc = fill_u32(c, c->flags.p, kFlagCount, 0, st)) != BX_OK) return rc;
+  // The join kernel clears every group cursor it reads; they start at zero.
+  if ((rc = fill_u32(c, c->cnt2.p, ngsub, 0, st)) != BX_OK) return rc;
   c->stats.b1_bits = plan.b1bits;
   c->stats.b2_bits = plan.b2bits;
   c->stats.seg_len = c->seg_len;
@@ -420,22 +426,25 @@ int run_search(bx_ctx* c, Segs& s, int batch, uint32_t kinds, std::vector<OutPai
 
   const uint32_t gmask = batch ? kGrpMask : 0u;
   const uint64_t kmask1 = kM42 | (static_cast<uint64_t>(gmask) << kGrpShift);
-  std::deque<std::pair<uint32_t, uint32_t>> pending;
-  for (uint32_t v = 0; v < (1u << plan.pbits); ++v) pending.emplace_back(plan.pbits, v);
+  // Pass p keeps the keys with pass_hash in [p 2^32 / P, (p+1) 2^32 / P).
+  std::deque<std::pair<uint64_t, uint64_t>> pending;
+  for (uint64_t v = 0; v < plan.passes; ++v)
+    pending.emplace_back((v << 32) / plan.passes, ((v + 1) << 32) / plan.passes);
   uint32_t cand_before = 0;
   uint32_t* d_flags = static_cast<uint32_t*>(c->flags.p);
+  const uint32_t cpb = static_cast<uint32_t>((plan.cap1 + kPartChunk - 1) / kPartChunk);
+  const uint64_t part_grid = 8ull * ((cpb + (8 / G) - 1) / (8 / G));
+  if (part_grid > 0x7FFFFFFFull) return fail(BX_EINTERNAL, "partition grid too large");
   while (!pending.empty()) {
-    const uint32_t pbits = pending.front().first, pval = pending.front().second;
+    const uint64_t ph_lo = pending.front().first, ph_hi = pending.front().second;
     pending.pop_front();
-    if (pbits + plan.b1bits + plan.b2bits > 32) return fail(BX_EINTERNAL, "pass split exhausted the hash bits");
     if ((rc = fill_u32(c, c->cnt1.p, B1, 0, st)) != BX_OK) return rc;
-    if ((rc = fill_u32(c, c->cnt2.p, nsub, 0, st)) != BX_OK) return rc;
     SieveParams P = base_sieve_params(c, s);
     P.batch = batch;
-    P.pfilter = pbits > 0;
-    P.pshift = pbits > 0 ? 32 - pbits : 0;
-    P.pval = pval;
-    P.b1shift = plan.b1bits ? 32 - pbits - plan.b1bits : 0;
+    P.pfilter = !(ph_lo == 0 && ph_hi == (1ull << 32));
+    P.ph_lo = ph_lo;
+    P.ph_hi = ph_hi;
+    P.b1shift = plan.b1bits ? 32 - plan.b1bits : 0;
     P.b1mask = B1 - 1;
     P.l1 = static_cast<Entry*>(c->l1.p);
     P.cap1 = plan.cap1;
@@ -445,41 +454,42 @@ int run_search(bx_ctx* c, Segs& s, int batch, uint32_t kinds, std::vector<OutPai
       hipLaunchKernelGGL((k_sieve<kTile, kSieveBlock, MODE_KEYS>), dim3(sieve_grid), dim3(kSieveBlock), 0, st, P);
     }
     BX_HIP(hipGetLastError());
-    PartParams Q;
-    Q.l1 = static_cast<const Entry*>(c->l1.p);
-    Q.cap1 = plan.cap1;
-    Q.cnt1 = static_cast<const uint32_t*>(c->cnt1.p);
-    Q.B1 = B1;
-    Q.chunks_per_bucket = static_cast<uint32_t>((plan.cap1 + kPartChunk - 1) / kPartChunk);
-    Q.l2 = static_cast<Entry*>(c->l2.p);
-    Q.cap2 = plan.cap2;
-    Q.cnt2 = static_cast<uint32_t*>(c->cnt2.p);
-    Q.b2shift = plan.b2bits ? 32 - pbits - plan.b1bits - plan.b2bits : 0;
-    Q.b2mask = B2 - 1;
-    Q.gmask = gmask;
-    Q.flags = d_flags;
-    const uint64_t part_grid = 8ull * ((B1 + 7) / 8) * Q.chunks_per_bucket;
-    if (part_grid > 0x7FFFFFFFull) return fail(BX_EINTERNAL, "partition grid too large");
-    {
-      LaunchTimer t(c, K_PART, st);
-      hipLaunchKernelGGL((k_partition<kPartBlock>), dim3(static_cast<uint32_t>(part_grid)), dim3(kPartBlock), 0, st, Q);
+    for (uint32_t first = 0; first < B1; first += G) {
+      PartParams Q;
+      Q.l1 = static_cast<const Entry*>(c->l1.p);
+      Q.cap1 = plan.cap1;
+      Q.cnt1 = static_cast<const uint32_t*>(c->cnt1.p);
+      Q.first = first;
+      Q.G = G;
+      Q.chunks_per_bucket = cpb;
+      Q.l2 = static_cast<Entry*>(c->l2.p);
+      Q.cap2 = plan.cap2;
+      Q.cnt2 = static_cast<uint32_t*>(c->cnt2.p);
+      Q.b2shift = plan.b2bits ? 32 - plan.b1bits - plan.b2bits : 0;
+      Q.b2mask = B2 - 1;
+      Q.gmask = gmask;
+      Q.flags = d_flags;
+      {
+        LaunchTimer t(c, K_PART, st);
+        hipLaunchKernelGGL((k_partition<kPartBlock>), dim3(static_cast<uint32_t>(part_grid)), dim3(kPartBlock), 0, st, Q);
+      }
+      BX_HIP(hipGetLastError());
+      JoinParams J;
+      J.l2 = static_cast<const Entry*>(c->l2.p);
+      J.cap2 = plan.cap2;
+      J.cnt2 = static_cast<uint32_t*>(c->cnt2.p);
+      J.n_sub = ngsub;
+      J.kmask1 = kmask1;
+      J.gmask = gmask;
+      J.cand = static_cast<Cand*>(c->cand.p);
+      J.cand_cap = kCandCap;
+      J.flags = d_flags;
+      {
+        LaunchTimer t(c, K_JOIN, st);
+        hipLaunchKernelGGL((k_join<kJoinBlock>), dim3(static_cast<uint32_t>(ngsub)), dim3(kJoinBlock), 0, st, J);
+      }
+      BX_HIP(hipGetLastError());
     }
-    BX_HIP(hipGetLastError());
-    JoinParams J;
-    J.l2 = static_cast<const Entry*>(c->l2.p);
-    J.cap2 = plan.cap2;
-    J.cnt2 = static_cast<const uint32_t*>(c->cnt2.p);
-    J.n_sub = nsub;
-    J.kmask1 = kmask1;
-    J.gmask = gmask;
-    J.cand = static_cast<Cand*>(c->cand.p);
-    J.cand_cap = kCandCap;
-    J.flags = d_flags;
-    {
-      LaunchTimer t(c, K_JOIN, st);
-      hipLaunchKernelGGL((k_join<kJoinBlock>), dim3(static_cast<uint32_t>(nsub)), dim3(kJoinBlock), 0, st, J);
-    }
-    BX_HIP(hipGetLastError());
     uint32_t fl[kFlagCount];
     BX_HIP(hipMemcpyAsync(fl, d_flags, sizeof(fl), hipMemcpyDeviceToHost, st));
     BX_HIP(hipStreamSynchronize(st));
@@ -488,12 +498,14 @@ int run_search(bx_ctx* c, Segs& s, int batch, uint32_t kinds, std::vector<OutPai
     if (fl[kFlagL1Overflow] || fl[kFlagL2Overflow]) {
       // Discard this pass's candidates and run it again as two half passes.
       c->stats.retries++;
+      if (ph_hi - ph_lo < 2) return fail(BX_EINTERNAL, "bucket overflow on a single pass-hash value");
       uint32_t z[2] = {0, 0};
       BX_HIP(hipMemcpyAsync(d_flags + kFlagL1Overflow, z, sizeof(z), hipMemcpyHostToDevice, st));
       BX_HIP(hipMemcpyAsync(d_flags + kFlagCand, &cand_before, 4, hipMemcpyHostToDevice, st));
       BX_HIP(hipStreamSynchronize(st));
-      pending.emplace_front(pbits + 1, 2 * pval + 1);
-      pending.emplace_front(pbits + 1, 2 * pval);
+      const uint64_t mid = ph_lo + (ph_hi - ph_lo) / 2;
+      pending.emplace_front(mid, ph_hi);
+      pending.emplace_front(ph_lo, mid);
       continue;
     }
     cand_before = fl[kFlagCand];
@@ -756,7 +768,7 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
   std::lock_guard<std::mutex> lk(c->mu);
   const std::string n(name);
   if (n == "passes") {
-    if (v < 0 || (v & (v - 1))) return fail(BX_EINVAL, "passes must be 0 or a power of two");
+    if (v < 0 || v > 4096) return fail(BX_EINVAL, "passes must be in [0, 4096]");
     c->force_passes = static_cast<int>(v);
   } else if (n == "seg_len") {
     if (v == 0) v = kDefaultSegLen;
@@ -766,11 +778,14 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
     c->timing = v != 0;
   } else if (n == "verify") {
     c->verify = v != 0;
+  } else if (n == "group") {
+    if (v != 0 && v != 1 && v != 2 && v != 4 && v != 8) return fail(BX_EINVAL, "group must be 0, 1, 2, 4 or 8");
+    c->force_group = static_cast<int>(v);
   } else if (n == "b1_bits") {
     if (v > 10) return fail(BX_EINVAL, "b1_bits <= 10");
     c->force_b1 = v == 0 ? -1 : static_cast<int>(v);
   } else if (n == "b2_bits") {
-    if (v > 12) return fail(BX_EINVAL, "b2_bits <= 12");
+    if (v > 13) return fail(BX_EINVAL, "b2_bits <= 13");
     c->force_b2 = v == 0 ? -1 : static_cast<int>(v);
   } else {
     return fail(BX_EINVAL, "unknown option " + n);

@@ -132,7 +132,22 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
   return h;
 }
 
-// Hash of a join key (lo, hi, grp) for the pass / partition bits.  The key is
+// Cheap hash of a join key, evaluated for every x to pick its pass: 21-bit
+// limbs through full-rate 24-bit multiplies, then one xorshift-multiply round.
+// Any function of the key gives exact passes; this one only has to spread the
+// keys evenly.
+__device__ __forceinline__ uint32_t pass_hash(uint64_t lo, uint64_t hi, uint32_t grp) {
+  const uint32_t l0 = static_cast<uint32_t>(lo) & 0x1FFFFFu, l1 = static_cast<uint32_t>(lo >> 21);
+  const uint32_t h0 = static_cast<uint32_t>(hi) & 0x1FFFFFu, h1 = static_cast<uint32_t>(hi >> 21);
+  uint32_t s = __umul24(l0, 0x9E3779u) + __umul24(l1, 0x7F4A7Du) + __umul24(h0, 0xC2B2AFu) + __umul24(h1, 0x85EBCBu) +
+               __umul24(grp, 0x27D4EBu);
+  s ^= s >> 15;
+  s *= 0x2C1B3C6Du;
+  s ^= s >> 12;
+  return s;
+}
+
+// Hash of a join key (lo, hi, grp) for the partition bits.  The key is
 // canonical (lo < hi), so the hash is the same for both orders of the set.
 __device__ __forceinline__ uint32_t key_hash(uint64_t lo, uint64_t hi, uint32_t grp) {
   const uint32_t c = (static_cast<uint32_t>(lo >> 32) | (static_cast<uint32_t>(hi >> 32) << 10)) + grp * 0x01000193u;

@@ -25,7 +25,7 @@ constexpr int MODE_KEYS = 1;
 constexpr int kHitCap = 1024;      // sparse-hit list held in LDS per segment
 constexpr int kStageCap = 4096;    // staged entries per workgroup before a flush
 constexpr int kB1Max = 1024;       // first partition fan-out
-constexpr int kB2Max = 4096;       // second partition fan-out
+constexpr int kB2Max = 8192;       // second partition fan-out
 constexpr int kPartChunk = 4096;   // entries per workgroup in k_partition
 constexpr int kJoinCap = 3072;     // entries of one LDS join chunk
 constexpr int kJoinSlots = 8192;   // LDS hash-table slots (load <= 0.375)
@@ -48,7 +48,8 @@ struct SieveParams {
   uint64_t rad_lo, rad_hi;
   // MODE_KEYS
   int batch;
-  uint32_t pfilter, pshift, pval;
+  uint32_t pfilter;       // keep x only when pass_hash(key) is in [ph_lo, ph_hi)
+  uint64_t ph_lo, ph_hi;
   uint32_t b1shift, b1mask;
   Entry* l1;
   uint64_t cap1;
@@ -68,8 +69,8 @@ struct SieveShCommon {
 template <int T, int BLOCK>
 struct SieveShKeys : SieveShCommon<T, BLOCK> {
   Entry stage[kStageCap];
-  uint16_t sb[kStageCap], rank[kStageCap], perm[kStageCap];
-  uint32_t hist[kB1Max], off[kB1Max], gbase[kB1Max];
+  uint16_t sb[kStageCap], perm[kStageCap];
+  uint32_t cnt[kB1Max], gofs[kB1Max];
 };
 
 template <int T, int BLOCK, int MODE>
@@ -81,41 +82,66 @@ struct SieveShSel<T, BLOCK, MODE_KEYS> {
   using type = SieveShKeys<T, BLOCK>;
 };
 
-// Write the staged entries to their first-level buckets: counting sort by
-// bucket in LDS, one global reservation per non-empty bucket, then runs of
-// consecutive entries per bucket (coalesced 16 B stores).
-template <int T, int BLOCK>
-__device__ void flush_stage(SieveShKeys<T, BLOCK>& sh, const SieveParams& P) {
+// Counting sort of n staged entries (bucket of entry i in sb[i]) into runs per
+// bucket: LDS histogram, one global reservation per non-empty bucket, then the
+// runs are written with consecutive threads on consecutive entries (coalesced
+// stores).  cnt/gofs hold NB words; perm holds n.  gcur[b] is the global cursor
+// of bucket b and dst(b, k) the address of its k-th slot (k < cap).
+template <int BLOCK, int NB, typename Dst>
+__device__ void scatter_runs(uint32_t n, uint32_t nb, const Entry* ent, const uint16_t* sb, uint16_t* perm,
+                             uint32_t* cnt, uint32_t* gofs, uint32_t* wsum, uint32_t* gcur, uint64_t cap,
+                             uint32_t* flag, Dst dst) {
+  constexpr int BINS = (NB + BLOCK - 1) / BLOCK;
   const int tid = threadIdx.x;
+  for (uint32_t b = tid; b < nb; b += BLOCK) cnt[b] = 0;
   __syncthreads();
-  const uint32_t n = sh.stage_n;
-  const uint32_t B1 = P.b1mask + 1;
-  for (uint32_t b = tid; b < B1; b += BLOCK) sh.hist[b] = 0;
+  for (uint32_t i = tid; i < n; i += BLOCK) atomicAdd(&cnt[sb[i]], 1u);
   __syncthreads();
-  for (uint32_t i = tid; i < n; i += BLOCK) sh.rank[i] = static_cast<uint16_t>(atomicAdd(&sh.hist[sh.sb[i]], 1u));
-  __syncthreads();
-  static_assert(kB1Max <= BLOCK || BLOCK >= 1024, "one bucket per thread");
-  const uint32_t c = static_cast<uint32_t>(tid) < B1 ? sh.hist[tid] : 0u;
+  uint32_t loc[BINS];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < BINS; ++k) {
+    const uint32_t b = tid * BINS + k;
+    loc[k] = b < nb ? cnt[b] : 0u;
+    sum += loc[k];
+  }
   uint32_t tot;
-  const uint32_t ex = block_exclusive_scan<BLOCK>(c, sh.wsum, &tot);
-  if (static_cast<uint32_t>(tid) < B1) {
-    sh.off[tid] = ex;
-    sh.gbase[tid] = c ? atomicAdd(&P.cnt1[tid], c) : 0u;
+  uint32_t ex = block_exclusive_scan<BLOCK>(sum, wsum, &tot);
+#pragma unroll
+  for (int k = 0; k < BINS; ++k) {
+    const uint32_t b = tid * BINS + k;
+    if (b < nb) {
+      const uint32_t g = loc[k] ? atomicAdd(&gcur[b], loc[k]) : 0u;
+      gofs[b] = g - ex;  // slot j of the sorted order lands at run position g + (j - ex)
+      cnt[b] = ex;       // becomes the LDS cursor of bucket b
+    }
+    ex += loc[k];
   }
   __syncthreads();
-  for (uint32_t i = tid; i < n; i += BLOCK) sh.perm[sh.off[sh.sb[i]] + sh.rank[i]] = static_cast<uint16_t>(i);
+  for (uint32_t i = tid; i < n; i += BLOCK) perm[atomicAdd(&cnt[sb[i]], 1u)] = static_cast<uint16_t>(i);
   __syncthreads();
   for (uint32_t j = tid; j < n; j += BLOCK) {
-    const uint32_t i = sh.perm[j];
-    const uint32_t b = sh.sb[i];
-    const uint64_t k = static_cast<uint64_t>(sh.gbase[b]) + (j - sh.off[b]);
-    if (k < P.cap1)
-      P.l1[static_cast<uint64_t>(b) * P.cap1 + k] = sh.stage[i];
+    const uint32_t i = perm[j];
+    const uint32_t b = sb[i];
+    const uint32_t k = gofs[b] + j;
+    if (k < cap)
+      dst(b, k, ent[i]);
     else
-      atomicOr(&P.flags[kFlagL1Overflow], 1u);
+      atomicOr(flag, 1u);
   }
   __syncthreads();
-  if (tid == 0) sh.stage_n = 0;
+}
+
+template <int T, int BLOCK>
+__device__ void flush_stage(SieveShKeys<T, BLOCK>& sh, const SieveParams& P) {
+  __syncthreads();
+  const uint32_t n = sh.stage_n;
+  Entry* l1 = P.l1;
+  const uint64_t cap1 = P.cap1;
+  scatter_runs<BLOCK, kB1Max>(n, P.b1mask + 1, sh.stage, sh.sb, sh.perm, sh.cnt, sh.gofs, sh.wsum, P.cnt1, cap1,
+                              &P.flags[kFlagL1Overflow],
+                              [=](uint32_t b, uint32_t k, const Entry& e) { l1[static_cast<uint64_t>(b) * cap1 + k] = e; });
+  if (threadIdx.x == 0) sh.stage_n = 0;
   __syncthreads();
 }
 
@@ -232,10 +258,14 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
           if (i < cnt) {
             const uint64_t a = sh.tile[i], b = sh.tile[i + 1];
             const uint64_t klo = a < b ? a : b, khi = a < b ? b : a;
-            const uint32_t h = key_hash(klo, khi, grp);
-            keep = !P.pfilter || (h >> P.pshift) == P.pval;
+            if (P.pfilter) {
+              const uint64_t ph = pass_hash(klo, khi, grp);
+              keep = ph >= P.ph_lo && ph < P.ph_hi;
+            } else {
+              keep = true;
+            }
             if (keep) {
-              b1 = (h >> P.b1shift) & P.b1mask;
+              b1 = (key_hash(klo, khi, grp) >> P.b1shift) & P.b1mask;
               const uint64_t x = x0 + i;
               en = make_entry(klo, khi, P.batch ? x - qa : x, grp, a > b ? 1u : 0u);
             }
@@ -266,39 +296,40 @@ struct PartParams {
   const Entry* l1;
   uint64_t cap1;
   const uint32_t* cnt1;
-  uint32_t B1;
+  uint32_t first;  // first first-level bucket of this group
+  uint32_t G;      // buckets in the group: 1, 2, 4 or 8
   uint32_t chunks_per_bucket;
-  Entry* l2;
+  Entry* l2;       // group buffer: G x B2 sub-buckets of cap2 entries
   uint32_t cap2;
-  uint32_t* cnt2;
+  uint32_t* cnt2;  // G x B2 cursors (zero on entry)
   uint32_t b2shift, b2mask;
   uint32_t gmask;
   uint32_t* flags;
 };
 
-// Second scatter: one chunk of a first-level bucket per workgroup.  Workgroup
-// l runs on XCD l mod 8 (round-robin dispatch); the mapping keeps every chunk
-// of a bucket on one XCD so the partially written lines of its sub-buckets
-// stay in that XCD's L2 until they are complete.
+// Second scatter of one group of first-level buckets into the group buffer.
+// Workgroup l runs on XCD l mod 8 (round-robin dispatch); with G = 8 every
+// chunk of a bucket stays on one XCD, so the partial lines of its sub-buckets
+// are completed in that XCD's L2 before they are written back.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
   __shared__ Entry ent[kPartChunk];
-  __shared__ uint16_t sb[kPartChunk], rank[kPartChunk], perm[kPartChunk];
-  __shared__ uint32_t hist[kB2Max], off[kB2Max], gbase[kB2Max];
+  __shared__ uint16_t sb[kPartChunk], perm[kPartChunk];
+  __shared__ uint32_t cnt[kB2Max], gofs[kB2Max];
   __shared__ uint32_t wsum[BLOCK / 64];
   const int tid = threadIdx.x;
   const uint32_t l = blockIdx.x;
   const uint32_t xcd = l & 7u, slot = l >> 3;
-  const uint32_t jb = slot / P.chunks_per_bucket, chunk = slot % P.chunks_per_bucket;
-  const uint32_t b1 = jb * 8u + xcd;
-  if (b1 >= P.B1) return;
+  const uint32_t per = 8u / P.G;
+  const uint32_t gb = xcd % P.G;
+  const uint32_t chunk = slot * per + xcd / P.G;
+  const uint32_t b1 = P.first + gb;
+  if (chunk >= P.chunks_per_bucket) return;
   const uint64_t n1 = min(static_cast<uint64_t>(P.cnt1[b1]), P.cap1);
   const uint64_t s0 = static_cast<uint64_t>(chunk) * kPartChunk;
   if (s0 >= n1) return;
   const uint32_t n = static_cast<uint32_t>(min(static_cast<uint64_t>(kPartChunk), n1 - s0));
   const Entry* src = P.l1 + static_cast<uint64_t>(b1) * P.cap1 + s0;
-  const uint32_t B2 = P.b2mask + 1;
-  for (uint32_t b = tid; b < B2; b += BLOCK) hist[b] = 0;
   for (uint32_t i = tid; i < n; i += BLOCK) {
     const Entry e = src[i];
     ent[i] = e;
@@ -306,47 +337,18 @@ __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
     sb[i] = static_cast<uint16_t>((h >> P.b2shift) & P.b2mask);
   }
   __syncthreads();
-  for (uint32_t i = tid; i < n; i += BLOCK) rank[i] = static_cast<uint16_t>(atomicAdd(&hist[sb[i]], 1u));
-  __syncthreads();
-  // Exclusive scan over B2 bins, BINS consecutive bins per thread.
-  constexpr int BINS = kB2Max / BLOCK;
-  uint32_t loc[BINS];
-  uint32_t sum = 0;
-#pragma unroll
-  for (int k = 0; k < BINS; ++k) {
-    const uint32_t b = tid * BINS + k;
-    loc[k] = b < B2 ? hist[b] : 0u;
-    sum += loc[k];
-  }
-  uint32_t tot;
-  uint32_t ex = block_exclusive_scan<BLOCK>(sum, wsum, &tot);
-#pragma unroll
-  for (int k = 0; k < BINS; ++k) {
-    const uint32_t b = tid * BINS + k;
-    if (b < B2) {
-      off[b] = ex;
-      gbase[b] = loc[k] ? atomicAdd(&P.cnt2[static_cast<uint64_t>(b1) * B2 + b], loc[k]) : 0u;
-    }
-    ex += loc[k];
-  }
-  __syncthreads();
-  for (uint32_t i = tid; i < n; i += BLOCK) perm[off[sb[i]] + rank[i]] = static_cast<uint16_t>(i);
-  __syncthreads();
-  for (uint32_t j = tid; j < n; j += BLOCK) {
-    const uint32_t i = perm[j];
-    const uint32_t b = sb[i];
-    const uint64_t k = static_cast<uint64_t>(gbase[b]) + (j - off[b]);
-    if (k < P.cap2)
-      P.l2[(static_cast<uint64_t>(b1) * B2 + b) * P.cap2 + k] = ent[i];
-    else
-      atomicOr(&P.flags[kFlagL2Overflow], 1u);
-  }
+  const uint32_t B2 = P.b2mask + 1;
+  Entry* out = P.l2 + static_cast<uint64_t>(gb) * B2 * P.cap2;
+  const uint32_t cap2 = P.cap2;
+  scatter_runs<BLOCK, kB2Max>(n, B2, ent, sb, perm, cnt, gofs, wsum, P.cnt2 + static_cast<uint64_t>(gb) * B2, cap2,
+                              &P.flags[kFlagL2Overflow],
+                              [=](uint32_t b, uint32_t k, const Entry& e) { out[static_cast<uint64_t>(b) * cap2 + k] = e; });
 }
 
 struct JoinParams {
   const Entry* l2;
   uint32_t cap2;
-  const uint32_t* cnt2;
+  uint32_t* cnt2;
   uint64_t n_sub;
   uint64_t kmask1;
   uint32_t gmask;
@@ -381,6 +383,9 @@ __global__ __launch_bounds__(BLOCK) void k_join(JoinParams P) {
   const uint64_t sbk = blockIdx.x;
   if (sbk >= P.n_sub) return;
   const uint32_t n = min(P.cnt2[sbk], P.cap2);
+  __syncthreads();
+  // This workgroup is the only reader of the cursor: clear it for the next group.
+  if (tid == 0) P.cnt2[sbk] = 0;
   if (n < 2) return;
   const Entry* src = P.l2 + sbk * P.cap2;
   for (uint32_t i0 = 0; i0 < n; i0 += kJoinCap) {
