@@ -40,10 +40,11 @@ int fail(int code, const std::string& msg) {
     if (e_ != hipSuccess) return fail(BX_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int kTile = 4096;
-constexpr int kSieveBlock = 1024;
+constexpr int kTile = 2048;
+constexpr int kSieveBlock = 512;
+constexpr int kSieveWgPerCu = 2;  // LDS (< 80 KB per workgroup) allows two per CU
 constexpr int kPartBlock = 1024;
-constexpr int kJoinBlock = 256;
+constexpr int kJoinBlock = 512;
 constexpr int kVerifyBlock = 256;
 constexpr uint32_t kCandCap = 1u << 20;
 constexpr uint32_t kDefaultSegLen = 1u << 17;
@@ -298,6 +299,7 @@ int make_plan(bx_ctx* c, uint64_t n_keys, uint32_t sieve_grid, Plan* out) {
   const uint64_t fixed = fixed_bytes(c, sieve_grid);
   const uint32_t p_first = c->force_passes > 0 ? static_cast<uint32_t>(c->force_passes) : 1;
   const uint32_t p_last = c->force_passes > 0 ? p_first : 4096;
+  const double W = static_cast<double>(sieve_grid);
   for (uint32_t P = p_first; P <= p_last; ++P) {
     Plan p;
     p.passes = P;
@@ -305,23 +307,27 @@ int make_plan(bx_ctx* c, uint64_t n_keys, uint32_t sieve_grid, Plan* out) {
     uint32_t b1 = n_pass > 16384.0 ? std::min<uint32_t>(10, ceil_log2(n_pass / 16384.0)) : 0;
     if (c->force_b1 >= 0) b1 = static_cast<uint32_t>(c->force_b1);
     p.b1bits = b1;
-    p.cap1 = round_up(static_cast<uint64_t>(std::ceil(n_pass / std::ldexp(1.0, static_cast<int>(b1)) * 1.03)) + 2048, 64);
-    uint32_t b2 = p.cap1 > 2400 ? ceil_log2(static_cast<double>(p.cap1) / 2400.0) : 0;
+    const double bucket = n_pass / std::ldexp(1.0, static_cast<int>(b1));
+    // Each sieve workgroup owns one region per bucket (no atomics); its share
+    // of a bucket is bucket / W entries, plus slack.
+    p.cap1 = round_up(static_cast<uint64_t>(std::ceil(bucket / W * 1.05)) + 256, 64);
+    // Partitions of at most ~7.4k entries (one LDS join chunk holds 8192).
+    uint32_t b2 = bucket * 1.03 > 6500.0 ? ceil_log2(bucket * 1.03 / 6500.0) : 0;
     if (c->force_b2 >= 0) b2 = static_cast<uint32_t>(c->force_b2);
-    if (b2 > 13 || b1 + b2 > 32) {
+    if (b2 > 11 || b1 + b2 > 32) {
       if (c->force_passes > 0) return fail(BX_ENOMEM, "forced pass count leaves partitions too large");
       continue;
     }
     p.b2bits = b2;
     p.cap2 = static_cast<uint32_t>(
-        round_up(static_cast<uint64_t>(std::ceil(static_cast<double>(p.cap1) / std::ldexp(1.0, static_cast<int>(b2)) * 1.25)) + 64,
-                 16));
-    if (p.cap1 > 0xF0000000ull) continue;
+        round_up(static_cast<uint64_t>(std::ceil(bucket * 1.03 / std::ldexp(1.0, static_cast<int>(b2)) * 1.1)) + 128, 16));
+    if (p.cap1 > 0xF0000000ull || p.cap2 > 0xF0000000ull) continue;
     const uint64_t nb1 = 1ull << b1, nb2 = 1ull << b2;
     uint32_t G = c->force_group > 0 ? static_cast<uint32_t>(c->force_group) : 8u;
     if (G > nb1) G = static_cast<uint32_t>(nb1);
     p.group = G;
-    p.bytes = nb1 * p.cap1 * sizeof(Entry) + G * nb2 * p.cap2 * sizeof(Entry) + (nb1 + G * nb2) * 4;
+    p.bytes = nb1 * sieve_grid * p.cap1 * sizeof(Entry) + G * nb2 * p.cap2 * sizeof(Entry) +
+              (nb1 * sieve_grid + G * nb2) * 4;
     if (p.bytes + fixed <= c->budget) {
       *out = p;
       return BX_OK;
@@ -402,14 +408,16 @@ int run_search(bx_ctx* c, Segs& s, int batch, uint32_t kinds, std::vector<OutPai
   make_segs(c, &s);
   if (s.n_segs == 0) return BX_OK;
   int rc;
-  const uint32_t sieve_grid = static_cast<uint32_t>(std::min<uint64_t>(s.n_segs, static_cast<uint64_t>(c->n_cu)));
+  const uint32_t sieve_grid =
+      static_cast<uint32_t>(std::min<uint64_t>(s.n_segs, static_cast<uint64_t>(c->n_cu) * kSieveWgPerCu));
   Plan plan;
   if ((rc = make_plan(c, s.n_keys, sieve_grid, &plan)) != BX_OK) return rc;
   const uint32_t B1 = 1u << plan.b1bits, B2 = 1u << plan.b2bits, G = plan.group;
   const uint64_t ngsub = static_cast<uint64_t>(G) * B2;  // sub-buckets of one group
-  if ((rc = ensure(c, c->l1, B1 * plan.cap1 * sizeof(Entry))) != BX_OK) return rc;
+  const uint64_t n_regions = static_cast<uint64_t>(B1) * sieve_grid;
+  if ((rc = ensure(c, c->l1, n_regions * plan.cap1 * sizeof(Entry))) != BX_OK) return rc;
   if ((rc = ensure(c, c->l2, ngsub * plan.cap2 * sizeof(Entry))) != BX_OK) return rc;
-  if ((rc = ensure(c, c->cnt1, B1 * 4ull)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->cnt1, n_regions * 4ull)) != BX_OK) return rc;
   if ((rc = ensure(c, c->cnt2, ngsub * 4ull)) != BX_OK) return rc;
   if ((rc = ensure(c, c->cand, kCandCap * sizeof(Cand))) != BX_OK) return rc;
   if ((rc = ensure(c, c->out, kCandCap * sizeof(OutPair))) != BX_OK) return rc;
@@ -432,13 +440,13 @@ int run_search(bx_ctx* c, Segs& s, int batch, uint32_t kinds, std::vector<OutPai
     pending.emplace_back((v << 32) / plan.passes, ((v + 1) << 32) / plan.passes);
   uint32_t cand_before = 0;
   uint32_t* d_flags = static_cast<uint32_t*>(c->flags.p);
-  const uint32_t cpb = static_cast<uint32_t>((plan.cap1 + kPartChunk - 1) / kPartChunk);
-  const uint64_t part_grid = 8ull * ((cpb + (8 / G) - 1) / (8 / G));
+  const uint32_t cpr = static_cast<uint32_t>((plan.cap1 + kPartChunk - 1) / kPartChunk);
+  const uint64_t chunks = static_cast<uint64_t>(sieve_grid) * cpr;  // per bucket
+  const uint64_t part_grid = 8ull * ((chunks + (8 / G) - 1) / (8 / G));
   if (part_grid > 0x7FFFFFFFull) return fail(BX_EINTERNAL, "partition grid too large");
   while (!pending.empty()) {
     const uint64_t ph_lo = pending.front().first, ph_hi = pending.front().second;
     pending.pop_front();
-    if ((rc = fill_u32(c, c->cnt1.p, B1, 0, st)) != BX_OK) return rc;
     SieveParams P = base_sieve_params(c, s);
     P.batch = batch;
     P.pfilter = !(ph_lo == 0 && ph_hi == (1ull << 32));
@@ -459,9 +467,10 @@ int run_search(bx_ctx* c, Segs& s, int batch, uint32_t kinds, std::vector<OutPai
       Q.l1 = static_cast<const Entry*>(c->l1.p);
       Q.cap1 = plan.cap1;
       Q.cnt1 = static_cast<const uint32_t*>(c->cnt1.p);
+      Q.W = sieve_grid;
       Q.first = first;
       Q.G = G;
-      Q.chunks_per_bucket = cpb;
+      Q.chunks_per_region = cpr;
       Q.l2 = static_cast<Entry*>(c->l2.p);
       Q.cap2 = plan.cap2;
       Q.cnt2 = static_cast<uint32_t*>(c->cnt2.p);
@@ -509,8 +518,8 @@ int run_search(bx_ctx* c, Segs& s, int batch, uint32_t kinds, std::vector<OutPai
       continue;
     }
     cand_before = fl[kFlagCand];
-    std::vector<uint32_t> counts(B1);
-    BX_HIP(hipMemcpyAsync(counts.data(), c->cnt1.p, B1 * 4, hipMemcpyDeviceToHost, st));
+    std::vector<uint32_t> counts(n_regions);
+    BX_HIP(hipMemcpyAsync(counts.data(), c->cnt1.p, n_regions * 4, hipMemcpyDeviceToHost, st));
     BX_HIP(hipStreamSynchronize(st));
     for (uint32_t v : counts) c->stats.entries += v;
   }
@@ -574,7 +583,7 @@ int radicals_into(bx_ctx* c, uint64_t lo, uint64_t hi, uint64_t* dev_out, hipStr
   int rc;
   if ((rc = upload_segs(c, s, st)) != BX_OK) return rc;
   if ((rc = ensure(c, c->flags, kFlagCount * 4)) != BX_OK) return rc;
-  const uint32_t grid = static_cast<uint32_t>(std::min<uint64_t>(s.n_segs, 3ull * c->n_cu));
+  const uint32_t grid = static_cast<uint32_t>(std::min<uint64_t>(s.n_segs, 4ull * c->n_cu));
   if ((rc = ensure(c, c->spill, static_cast<size_t>(grid) * spill_cap_of(c) * 8)) != BX_OK) return rc;
   if ((rc = fill_u32(c, c->flags.p, kFlagCount, 0, st)) != BX_OK) return rc;
   SieveParams P = base_sieve_params(c, s);
@@ -785,7 +794,7 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
     if (v > 10) return fail(BX_EINVAL, "b1_bits <= 10");
     c->force_b1 = v == 0 ? -1 : static_cast<int>(v);
   } else if (n == "b2_bits") {
-    if (v > 13) return fail(BX_EINVAL, "b2_bits <= 13");
+    if (v > 11) return fail(BX_EINVAL, "b2_bits <= 11");
     c->force_b2 = v == 0 ? -1 : static_cast<int>(v);
   } else {
     return fail(BX_EINVAL, "unknown option " + n);

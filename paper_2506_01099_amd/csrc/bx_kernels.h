@@ -23,12 +23,13 @@ constexpr int MODE_RAD = 0;
 constexpr int MODE_KEYS = 1;
 
 constexpr int kHitCap = 1024;      // sparse-hit list held in LDS per segment
-constexpr int kStageCap = 4096;    // staged entries per workgroup before a flush
+constexpr int kStageCap = 2048;    // staged entries per workgroup before a flush
 constexpr int kB1Max = 1024;       // first partition fan-out
-constexpr int kB2Max = 8192;       // second partition fan-out
+constexpr int kB2Max = 2048;       // second partition fan-out
 constexpr int kPartChunk = 4096;   // entries per workgroup in k_partition
-constexpr int kJoinCap = 3072;     // entries of one LDS join chunk
-constexpr int kJoinSlots = 8192;   // LDS hash-table slots (load <= 0.375)
+constexpr int kJoinCap = 8192;     // entries of one LDS join chunk (held in registers)
+constexpr int kJoinSlots = 16384;  // LDS hash-table slots (load <= 0.5)
+constexpr int kJoinIdxBits = 14;   // slot = tag (18 bits) << 14 | entry index
 
 struct SieveParams {
   const Query* queries;
@@ -51,9 +52,9 @@ struct SieveParams {
   uint32_t pfilter;       // keep x only when pass_hash(key) is in [ph_lo, ph_hi)
   uint64_t ph_lo, ph_hi;
   uint32_t b1shift, b1mask;
-  Entry* l1;
-  uint64_t cap1;
-  uint32_t* cnt1;
+  Entry* l1;       // region (b, w) of bucket b written by workgroup w: l1 + (b * gridDim.x + w) * cap1
+  uint64_t cap1;   // entries per region
+  uint32_t* cnt1;  // B1 x gridDim.x fill counts, written at the end of the kernel
 };
 
 template <int T, int BLOCK>
@@ -70,7 +71,7 @@ template <int T, int BLOCK>
 struct SieveShKeys : SieveShCommon<T, BLOCK> {
   Entry stage[kStageCap];
   uint16_t sb[kStageCap], perm[kStageCap];
-  uint32_t cnt[kB1Max], gofs[kB1Max];
+  uint32_t cnt[kB1Max], gofs[kB1Max], lcur[kB1Max];
 };
 
 template <int T, int BLOCK, int MODE>
@@ -85,9 +86,11 @@ struct SieveShSel<T, BLOCK, MODE_KEYS> {
 // Counting sort of n staged entries (bucket of entry i in sb[i]) into runs per
 // bucket: LDS histogram, one global reservation per non-empty bucket, then the
 // runs are written with consecutive threads on consecutive entries (coalesced
-// stores).  cnt/gofs hold NB words; perm holds n.  gcur[b] is the global cursor
-// of bucket b and dst(b, k) the address of its k-th slot (k < cap).
-template <int BLOCK, int NB, typename Dst>
+// stores).  cnt/gofs hold NB words; perm holds n.  gcur[b] is the cursor of
+// bucket b: shared by all workgroups (global, one atomic per non-empty bucket)
+// or, with PRIVATE, owned by this workgroup (no atomics).  dst(b, k) stores the
+// k-th entry of the bucket (k < cap).
+template <int BLOCK, int NB, bool PRIVATE, typename Dst>
 __device__ void scatter_runs(uint32_t n, uint32_t nb, const Entry* ent, const uint16_t* sb, uint16_t* perm,
                              uint32_t* cnt, uint32_t* gofs, uint32_t* wsum, uint32_t* gcur, uint64_t cap,
                              uint32_t* flag, Dst dst) {
@@ -111,7 +114,13 @@ __device__ void scatter_runs(uint32_t n, uint32_t nb, const Entry* ent, const ui
   for (int k = 0; k < BINS; ++k) {
     const uint32_t b = tid * BINS + k;
     if (b < nb) {
-      const uint32_t g = loc[k] ? atomicAdd(&gcur[b], loc[k]) : 0u;
+      uint32_t g;
+      if constexpr (PRIVATE) {  // gcur is this workgroup's own cursor array (LDS)
+        g = gcur[b];
+        gcur[b] = g + loc[k];
+      } else {
+        g = loc[k] ? atomicAdd(&gcur[b], loc[k]) : 0u;
+      }
       gofs[b] = g - ex;  // slot j of the sorted order lands at run position g + (j - ex)
       cnt[b] = ex;       // becomes the LDS cursor of bucket b
     }
@@ -136,11 +145,11 @@ template <int T, int BLOCK>
 __device__ void flush_stage(SieveShKeys<T, BLOCK>& sh, const SieveParams& P) {
   __syncthreads();
   const uint32_t n = sh.stage_n;
-  Entry* l1 = P.l1;
-  const uint64_t cap1 = P.cap1;
-  scatter_runs<BLOCK, kB1Max>(n, P.b1mask + 1, sh.stage, sh.sb, sh.perm, sh.cnt, sh.gofs, sh.wsum, P.cnt1, cap1,
-                              &P.flags[kFlagL1Overflow],
-                              [=](uint32_t b, uint32_t k, const Entry& e) { l1[static_cast<uint64_t>(b) * cap1 + k] = e; });
+  const uint64_t cap1 = P.cap1, W = gridDim.x;
+  Entry* l1 = P.l1 + static_cast<uint64_t>(blockIdx.x) * cap1;
+  scatter_runs<BLOCK, kB1Max, true>(n, P.b1mask + 1, sh.stage, sh.sb, sh.perm, sh.cnt, sh.gofs, sh.wsum, sh.lcur, cap1,
+                                    &P.flags[kFlagL1Overflow],
+                                    [=](uint32_t b, uint32_t k, const Entry& e) { l1[b * W * cap1 + k] = e; });
   if (threadIdx.x == 0) sh.stage_n = 0;
   __syncthreads();
 }
@@ -160,6 +169,9 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
   }
   for (uint32_t i = tid; i < nslots; i += BLOCK) sh.slot_d[i] = D->slot_d[i];
   if (tid == 0) sh.stage_n = 0;
+  if constexpr (MODE == MODE_KEYS) {
+    for (uint32_t b = tid; b < kB1Max; b += BLOCK) sh.lcur[b] = 0;
+  }
   __syncthreads();
   uint64_t* spill = P.spill + static_cast<uint64_t>(blockIdx.x) * P.spill_cap;
 
@@ -289,16 +301,18 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
   if constexpr (MODE == MODE_KEYS) {
     __syncthreads();
     if (sh.stage_n > 0) flush_stage<T, BLOCK>(sh, P);
+    for (uint32_t b = tid; b <= P.b1mask; b += BLOCK) P.cnt1[static_cast<uint64_t>(b) * gridDim.x + blockIdx.x] = sh.lcur[b];
   }
 }
 
 struct PartParams {
   const Entry* l1;
-  uint64_t cap1;
-  const uint32_t* cnt1;
+  uint64_t cap1;          // entries per first-level region
+  const uint32_t* cnt1;   // B1 x W region fill counts
+  uint32_t W;             // regions per bucket (sieve workgroups)
   uint32_t first;  // first first-level bucket of this group
   uint32_t G;      // buckets in the group: 1, 2, 4 or 8
-  uint32_t chunks_per_bucket;
+  uint32_t chunks_per_region;
   Entry* l2;       // group buffer: G x B2 sub-buckets of cap2 entries
   uint32_t cap2;
   uint32_t* cnt2;  // G x B2 cursors (zero on entry)
@@ -324,12 +338,14 @@ __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
   const uint32_t gb = xcd % P.G;
   const uint32_t chunk = slot * per + xcd / P.G;
   const uint32_t b1 = P.first + gb;
-  if (chunk >= P.chunks_per_bucket) return;
-  const uint64_t n1 = min(static_cast<uint64_t>(P.cnt1[b1]), P.cap1);
-  const uint64_t s0 = static_cast<uint64_t>(chunk) * kPartChunk;
+  const uint32_t w = chunk / P.chunks_per_region, j = chunk % P.chunks_per_region;
+  if (w >= P.W) return;
+  const uint64_t region = static_cast<uint64_t>(b1) * P.W + w;
+  const uint64_t n1 = min(static_cast<uint64_t>(P.cnt1[region]), P.cap1);
+  const uint64_t s0 = static_cast<uint64_t>(j) * kPartChunk;
   if (s0 >= n1) return;
   const uint32_t n = static_cast<uint32_t>(min(static_cast<uint64_t>(kPartChunk), n1 - s0));
-  const Entry* src = P.l1 + static_cast<uint64_t>(b1) * P.cap1 + s0;
+  const Entry* src = P.l1 + region * P.cap1 + s0;
   for (uint32_t i = tid; i < n; i += BLOCK) {
     const Entry e = src[i];
     ent[i] = e;
@@ -340,7 +356,7 @@ __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
   const uint32_t B2 = P.b2mask + 1;
   Entry* out = P.l2 + static_cast<uint64_t>(gb) * B2 * P.cap2;
   const uint32_t cap2 = P.cap2;
-  scatter_runs<BLOCK, kB2Max>(n, B2, ent, sb, perm, cnt, gofs, wsum, P.cnt2 + static_cast<uint64_t>(gb) * B2, cap2,
+  scatter_runs<BLOCK, kB2Max, false>(n, B2, ent, sb, perm, cnt, gofs, wsum, P.cnt2 + static_cast<uint64_t>(gb) * B2, cap2,
                               &P.flags[kFlagL2Overflow],
                               [=](uint32_t b, uint32_t k, const Entry& e) { out[static_cast<uint64_t>(b) * cap2 + k] = e; });
 }
@@ -371,14 +387,19 @@ __device__ __forceinline__ void emit_cand(const JoinParams& P, const Entry& a, c
 // chain to the first empty slot and compares the key with every occupied slot
 // on the way (Algorithm 3's insert step).  Two equal keys follow the same
 // chain, so the one that claims the later slot passes the other and reports
-// the pair; every pair of a group is reported once.  Partitions larger than
-// one LDS chunk are joined chunk by chunk: after chunk c is inserted, every
-// later entry probes it (walking to an empty slot, as the probe step does).
+// the pair; every pair of a group is reported once.  A slot holds an 18-bit
+// tag of the key hash and the entry's index; the entries themselves stay in
+// registers (EPT per thread), and the rare tag match re-reads the other entry
+// from the partition (L2-resident).  Partitions larger than one chunk are
+// joined chunk by chunk: after chunk c is inserted, every later entry probes
+// it, walking to an empty slot as the probe step does.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_join(JoinParams P) {
-  __shared__ Entry ent[kJoinCap];
-  __shared__ uint32_t table[kJoinSlots];
+  constexpr int EPT = kJoinCap / BLOCK;
   constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+  constexpr uint32_t kIdxMask = (1u << kJoinIdxBits) - 1;
+  static_assert(kJoinCap < (1 << kJoinIdxBits), "index field must not reach the empty marker");
+  __shared__ uint32_t table[kJoinSlots];
   const int tid = threadIdx.x;
   const uint64_t sbk = blockIdx.x;
   if (sbk >= P.n_sub) return;
@@ -390,14 +411,21 @@ __global__ __launch_bounds__(BLOCK) void k_join(JoinParams P) {
   const Entry* src = P.l2 + sbk * P.cap2;
   for (uint32_t i0 = 0; i0 < n; i0 += kJoinCap) {
     const uint32_t m = min(static_cast<uint32_t>(kJoinCap), n - i0);
+    Entry e[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const uint32_t i = tid + k * BLOCK;
+      if (i < m) e[k] = src[i0 + i];
+    }
     for (uint32_t s = tid; s < static_cast<uint32_t>(kJoinSlots); s += BLOCK) table[s] = kEmpty;
-    for (uint32_t i = tid; i < m; i += BLOCK) ent[i] = src[i0 + i];
     __syncthreads();
-    for (uint32_t i = tid; i < m; i += BLOCK) {
-      const Entry e = ent[i];
-      const uint64_t k0 = e.w0 & kM42, k1 = e.w1 & P.kmask1;
-      const uint32_t h = key_hash2(k0, e.w1 & kM42, entry_grp(e, P.gmask));
-      const uint32_t mine = (h & 0xFFFF0000u) | i;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const uint32_t i = tid + k * BLOCK;
+      if (i >= m) continue;
+      const uint64_t k0 = e[k].w0 & kM42, k1 = e[k].w1 & P.kmask1;
+      const uint32_t h = key_hash2(k0, e[k].w1 & kM42, entry_grp(e[k], P.gmask));
+      const uint32_t mine = (h & ~kIdxMask) | i;
       uint32_t s = h & (kJoinSlots - 1);
       for (;;) {
         uint32_t v = table[s];
@@ -405,25 +433,25 @@ __global__ __launch_bounds__(BLOCK) void k_join(JoinParams P) {
           v = atomicCAS(&table[s], kEmpty, mine);
           if (v == kEmpty) break;
         }
-        if (((v ^ mine) >> 16) == 0) {
-          const Entry f = ent[v & 0xFFFFu];
-          if ((f.w0 & kM42) == k0 && (f.w1 & P.kmask1) == k1) emit_cand(P, e, f);
+        if (((v ^ mine) & ~kIdxMask) == 0) {
+          const Entry f = src[i0 + (v & kIdxMask)];
+          if ((f.w0 & kM42) == k0 && (f.w1 & P.kmask1) == k1) emit_cand(P, e[k], f);
         }
         s = (s + 1) & (kJoinSlots - 1);
       }
     }
     __syncthreads();
     for (uint32_t jj = i0 + m + tid; jj < n; jj += BLOCK) {
-      const Entry e = src[jj];
-      const uint64_t k0 = e.w0 & kM42, k1 = e.w1 & P.kmask1;
-      const uint32_t h = key_hash2(k0, e.w1 & kM42, entry_grp(e, P.gmask));
+      const Entry g = src[jj];
+      const uint64_t k0 = g.w0 & kM42, k1 = g.w1 & P.kmask1;
+      const uint32_t h = key_hash2(k0, g.w1 & kM42, entry_grp(g, P.gmask));
       uint32_t s = h & (kJoinSlots - 1);
       for (;;) {
         const uint32_t v = table[s];
         if (v == kEmpty) break;
-        if (((v ^ h) >> 16) == 0) {
-          const Entry f = ent[v & 0xFFFFu];
-          if ((f.w0 & kM42) == k0 && (f.w1 & P.kmask1) == k1) emit_cand(P, e, f);
+        if (((v ^ h) & ~kIdxMask) == 0) {
+          const Entry f = src[i0 + (v & kIdxMask)];
+          if ((f.w0 & kM42) == k0 && (f.w1 & P.kmask1) == k1) emit_cand(P, g, f);
         }
         s = (s + 1) & (kJoinSlots - 1);
       }
