@@ -119,6 +119,19 @@ int bx_poll(bx_ctx* ctx, uint64_t ticket, int* done);
 int bx_take(bx_ctx* ctx, uint64_t ticket, bx_pair** out, size_t* count, double* t_submit, double* t_done);
 double bx_now(void);
 
+/* Autotuner.  Times the batched search of the queries [a[i], b[i]) (q >= 1;
+ * one query [1, N+1) stands for a plain search) under every combination of
+ * sieve tile {2048, 4096}, segment length {2^15 .. 2^19} and second-level group
+ * {2, 4, 8}, `reps` timed runs each after one warm-up, keeps the fastest,
+ * applies it to ctx and, when path is not NULL, writes it as a one-line JSON
+ * object (arch, tile, seg_len, group, ms).  Results of every run are checked
+ * to be identical.  Errors as bx_search_batch, plus BX_EDEVICE when a file
+ * cannot be written and BX_EINTERNAL when two settings disagree. */
+int bx_autotune(bx_ctx* ctx, const uint64_t* a, const uint64_t* b, size_t q, int reps, const char* path);
+/* Apply a tuning file written by bx_autotune; a file for another GPU
+ * architecture is ignored (returns BX_OK, nothing changes). */
+int bx_load_tuning(bx_ctx* ctx, const char* path);
+
 /* Statistics of the last completed call on this context (device times from HIP
  * events recorded on the stream the kernels ran on). */
 typedef struct {
@@ -133,6 +146,7 @@ typedef struct {
   double total_ms;            /* host wall time of the call                       */
   uint32_t b1_bits, b2_bits;  /* partition fan-outs used                          */
   uint32_t seg_len, tile;     /* segment length and LDS tile used by the sieve    */
+  double graph_ms;            /* device time of the captured graph (batched calls) */
 } bx_stats;
 int bx_get_stats(bx_ctx* ctx, bx_stats* out);
 
@@ -143,7 +157,9 @@ int bx_get_stats(bx_ctx* ctx, bx_stats* out);
  *   "verify"       1 = recompute every candidate by trial division (default 1)
  *   "b1_bits"      force the first partition fan-out (0 = plan)
  *   "b2_bits"      force the second partition fan-out (0 = plan)
- *   "group"        first-level buckets per second-level launch (1, 2, 4, 8; 0 = 8) */
+ *   "group"        first-level buckets per second-level launch (1, 2, 4, 8; 0 = 8)
+ *   "tile"         sieve LDS tile: 2048 (two workgroups per CU) or 4096 (0 = 2048)
+ *   "graph"        1 = batched calls run as one captured HIP graph (default 1)  */
 int bx_set_option(bx_ctx* ctx, const char* name, int64_t value);
 
 void bx_free(void* p);

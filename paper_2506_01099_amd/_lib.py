@@ -18,6 +18,7 @@ EXPORTS = [
     "bx_create", "bx_destroy", "bx_set_stream", "bx_radical_segment", "bx_radical_segment_dev",
     "bx_benelux_search", "bx_search_range", "bx_search_batch", "bx_serve_start", "bx_serve_stop",
     "bx_submit", "bx_poll", "bx_take", "bx_now", "bx_get_stats", "bx_set_option", "bx_free",
+    "bx_autotune", "bx_load_tuning",
     "bx_last_error", "benelux_search", "radical_segment",
 ]
 
@@ -39,7 +40,7 @@ class Stats(ctypes.Structure):
                 ("candidates", ctypes.c_uint64), ("pairs", ctypes.c_uint64),
                 ("launches", ctypes.c_uint32 * 5), ("kernel_ms", ctypes.c_double * 5),
                 ("total_ms", ctypes.c_double), ("b1_bits", ctypes.c_uint32), ("b2_bits", ctypes.c_uint32),
-                ("seg_len", ctypes.c_uint32), ("tile", ctypes.c_uint32)]
+                ("seg_len", ctypes.c_uint32), ("tile", ctypes.c_uint32), ("graph_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -82,6 +83,8 @@ def load():
         "bx_take": ([vp, u64, PP, ctypes.POINTER(sz), ctypes.POINTER(ctypes.c_double),
                      ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "bx_now": ([], ctypes.c_double),
+        "bx_autotune": ([vp, P64, P64, sz, ctypes.c_int, ctypes.c_char_p], ctypes.c_int),
+        "bx_load_tuning": ([vp, ctypes.c_char_p], ctypes.c_int),
         "bx_get_stats": ([vp, ctypes.POINTER(Stats)], ctypes.c_int),
         "bx_set_option": ([vp, ctypes.c_char_p, ctypes.c_int64], ctypes.c_int),
         "bx_free": ([vp], None),

@@ -69,8 +69,19 @@ class Benelux:
             "candidates": st.candidates, "pairs": st.pairs,
             "launches": dict(zip(names, list(st.launches))), "kernel_ms": dict(zip(names, list(st.kernel_ms))),
             "total_ms": st.total_ms, "b1_bits": st.b1_bits, "b2_bits": st.b2_bits,
-            "seg_len": st.seg_len, "tile": st.tile,
+            "seg_len": st.seg_len, "tile": st.tile, "graph_ms": st.graph_ms,
         }
+
+    def autotune(self, a, b, reps=1, path=None):
+        """Sweep tile / segment length / group on the queries [a[i], b[i]); keep the fastest."""
+        a = np.ascontiguousarray(a, dtype=np.uint64)
+        b = np.ascontiguousarray(b, dtype=np.uint64)
+        P64 = ctypes.POINTER(ctypes.c_uint64)
+        check(self._lib.bx_autotune(self._h, a.ctypes.data_as(P64), b.ctypes.data_as(P64), a.size, int(reps),
+                                    None if path is None else str(path).encode()))
+
+    def load_tuning(self, path):
+        check(self._lib.bx_load_tuning(self._h, str(path).encode()))
 
     # -- radicals ----------------------------------------------------------------------
     def radical_segment(self, lo, hi, out=None):

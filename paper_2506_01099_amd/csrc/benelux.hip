@@ -40,9 +40,10 @@ int fail(int code, const std::string& msg) {
     if (e_ != hipSuccess) return fail(BX_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int kTile = 2048;
-constexpr int kSieveBlock = 512;
-constexpr int kSieveWgPerCu = 2;  // LDS (< 80 KB per workgroup) allows two per CU
+// Two sieve shapes: LDS tiles of 2048 values with 512 threads (under 80 KB of
+// LDS, two workgroups per CU) or 4096 values with 1024 threads (one per CU).
+constexpr int kTileSmall = 2048, kTileLarge = 4096;
+constexpr int kVerifyGrid = 2048;
 constexpr int kPartBlock = 1024;
 constexpr int kJoinBlock = 512;
 constexpr int kVerifyBlock = 256;
@@ -96,14 +97,20 @@ struct bx_ctx {
   hipStream_t stream = nullptr;
   uint64_t hi_max = 0, budget = 0;
   int n_cu = 256;
+  std::string arch;
   std::vector<uint32_t> primes;
   std::vector<PrimePow> pp;
-  uint32_t n_dense = 0;
+  uint32_t n_dense[2] = {0, 0};  // per tile shape (small, large)
   uint32_t* d_primes = nullptr;
   PrimePow* d_pp = nullptr;
-  DenseTab* d_dense = nullptr;
-  DevBuf l1, l2, cnt1, cnt2, cand, out, flags, spill, queries, segpref, rad;
+  DenseTab* d_dense[2] = {nullptr, nullptr};
+  DevBuf l1, l2, cnt1, cnt2, cand, out, flags, spill, queries, segpref, rad, acc;
   int force_passes = 0, timing = 1, verify = 1, force_b1 = -1, force_b2 = -1, force_group = 0;
+  int tile = kTileSmall;
+  int graph_batch = 1;      // batched calls run as one captured HIP graph
+  bool capturing = false;   // no event records while a stream capture is open
+  hipGraphExec_t graph_exec = nullptr;
+  std::string graph_key;
   uint32_t seg_len = kDefaultSegLen;
   bx_stats stats{};
   std::mutex mu;
@@ -161,7 +168,7 @@ struct LaunchTimer {
   hipStream_t s;
   LaunchTimer(bx_ctx* ctx, int k, hipStream_t st) : c(ctx), kind(k), s(st) {
     c->stats.launches[k]++;
-    if (c->timing) {
+    if (c->timing && !c->capturing) {
       a = get_event(c);
       b = get_event(c);
       if (a) (void)hipEventRecord(a, s);
@@ -219,7 +226,7 @@ int fill_u32(bx_ctx* c, void* p, uint64_t n, uint32_t v, hipStream_t s) {
 
 // Prime tables: primes <= isqrt(hi_max) (for verification) and every odd prime
 // power p^k <= hi_max, k >= 2 (Algorithm 1 sieves with exactly these), sorted
-// by q, plus the dense schedule for the powers <= kTile.
+// by q, plus the dense schedules for the powers <= each tile size.
 int build_tables(bx_ctx* c) {
   const uint64_t lim = isqrt64(c->hi_max);
   std::vector<uint8_t> comp(lim + 1, 0);
@@ -241,34 +248,37 @@ int build_tables(bx_ctx* c) {
     }
   }
   std::sort(c->pp.begin(), c->pp.end(), [](const PrimePow& a, const PrimePow& b) { return a.q < b.q; });
-  DenseTab dt;
-  std::memset(&dt, 0, sizeof(dt));
-  uint32_t nd = 0, slots = 0;
-  for (const auto& w : c->pp) {
-    if (w.q > static_cast<uint64_t>(kTile)) break;
-    if (nd >= static_cast<uint32_t>(kDenseMax)) return fail(BX_EINTERNAL, "dense prime-power table overflow");
-    const uint32_t q = static_cast<uint32_t>(w.q);
-    const uint32_t ub = kTile / q + 1;  // multiples of q among T + 1 consecutive values
-    if (slots + ub > static_cast<uint32_t>(kDenseSlotMax)) return fail(BX_EINTERNAL, "dense slot table overflow");
-    dt.q[nd] = q;
-    dt.p[nd] = w.p;
-    dt.pinv[nd] = w.pinv;
-    dt.prefix[nd] = slots;
-    for (uint32_t k = 0; k < ub; ++k) dt.slot_d[slots + k] = static_cast<uint8_t>(nd);
-    slots += ub;
-    ++nd;
+  for (int which = 0; which < 2; ++which) {
+    const uint32_t T = which ? kTileLarge : kTileSmall;
+    DenseTab dt;
+    std::memset(&dt, 0, sizeof(dt));
+    uint32_t nd = 0, slots = 0;
+    for (const auto& w : c->pp) {
+      if (w.q > T) break;
+      if (nd >= static_cast<uint32_t>(kDenseMax)) return fail(BX_EINTERNAL, "dense prime-power table overflow");
+      const uint32_t q = static_cast<uint32_t>(w.q);
+      const uint32_t ub = T / q + 1;  // multiples of q among T + 1 consecutive values
+      if (slots + ub > static_cast<uint32_t>(kDenseSlotMax)) return fail(BX_EINTERNAL, "dense slot table overflow");
+      dt.q[nd] = q;
+      dt.p[nd] = w.p;
+      dt.pinv[nd] = w.pinv;
+      dt.prefix[nd] = slots;
+      for (uint32_t k = 0; k < ub; ++k) dt.slot_d[slots + k] = static_cast<uint8_t>(nd);
+      slots += ub;
+      ++nd;
+    }
+    dt.n = nd;
+    dt.nslots = slots;
+    c->n_dense[which] = nd;
+    BX_HIP(hipMalloc(&c->d_dense[which], sizeof(DenseTab)));
+    BX_HIP(hipMemcpy(c->d_dense[which], &dt, sizeof(DenseTab), hipMemcpyHostToDevice));
   }
-  dt.n = nd;
-  dt.nslots = slots;
-  c->n_dense = nd;
   BX_HIP(hipMalloc(&c->d_primes, std::max<size_t>(4, c->primes.size() * sizeof(uint32_t))));
   BX_HIP(hipMalloc(&c->d_pp, std::max<size_t>(sizeof(PrimePow), c->pp.size() * sizeof(PrimePow))));
-  BX_HIP(hipMalloc(&c->d_dense, sizeof(DenseTab)));
   if (!c->primes.empty())
     BX_HIP(hipMemcpy(c->d_primes, c->primes.data(), c->primes.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
   if (!c->pp.empty())
     BX_HIP(hipMemcpy(c->d_pp, c->pp.data(), c->pp.size() * sizeof(PrimePow), hipMemcpyHostToDevice));
-  BX_HIP(hipMemcpy(c->d_dense, &dt, sizeof(DenseTab), hipMemcpyHostToDevice));
   return BX_OK;
 }
 
@@ -281,7 +291,7 @@ uint32_t ceil_log2(double v) {
 uint64_t round_up(uint64_t v, uint64_t m) { return (v + m - 1) / m * m; }
 
 uint32_t spill_cap_of(const bx_ctx* c) {
-  return static_cast<uint32_t>(c->pp.size() - c->n_dense + c->seg_len / 128 + 64);
+  return static_cast<uint32_t>(c->pp.size() - c->n_dense[0] + c->seg_len / 128 + 64);
 }
 
 uint64_t fixed_bytes(const bx_ctx* c, uint32_t sieve_grid) {
@@ -380,8 +390,9 @@ SieveParams base_sieve_params(bx_ctx* c, const Segs& s) {
   P.seg_len = c->seg_len;
   P.pp = c->d_pp;
   P.n_pp = static_cast<uint32_t>(c->pp.size());
-  P.n_dense = c->n_dense;
-  P.dense = c->d_dense;
+  const int which = c->tile == kTileLarge ? 1 : 0;
+  P.n_dense = c->n_dense[which];
+  P.dense = c->d_dense[which];
   P.spill = static_cast<uint64_t*>(c->spill.p);
   P.spill_cap = spill_cap_of(c);
   P.flags = static_cast<uint32_t*>(c->flags.p);
@@ -395,122 +406,219 @@ int check_query(const bx_ctx* c, uint64_t a, uint64_t b) {
   return BX_OK;
 }
 
-// The hash-partitioned exact join over all queries of `s`.  Entries are
-// generated pass by pass; a pass whose buckets overflow is re-run split in
-// two (one more hash bit), so the result never depends on the bucket sizes.
-int run_search(bx_ctx* c, Segs& s, int batch, uint32_t kinds, std::vector<OutPair>* result) {
-  hipStream_t st = c->stream;
-  result->clear();
-  int rc0 = order_after_last(c, st);
-  if (rc0 != BX_OK) return rc0;
-  rc0 = mark_done(c, st);  // host-synchronous from here on: the call drains st
-  if (rc0 != BX_OK) return rc0;
-  make_segs(c, &s);
-  if (s.n_segs == 0) return BX_OK;
-  int rc;
-  const uint32_t sieve_grid =
-      static_cast<uint32_t>(std::min<uint64_t>(s.n_segs, static_cast<uint64_t>(c->n_cu) * kSieveWgPerCu));
+template <int MODE>
+void launch_sieve(const bx_ctx* c, const SieveParams& P, uint32_t grid, hipStream_t st) {
+  if (c->tile == kTileLarge)
+    hipLaunchKernelGGL((k_sieve<kTileLarge, 1024, MODE>), dim3(grid), dim3(1024), 0, st, P);
+  else
+    hipLaunchKernelGGL((k_sieve<kTileSmall, 512, MODE>), dim3(grid), dim3(512), 0, st, P);
+}
+
+// Sieve workgroups per CU for the key-generating sieve (LDS bound).
+uint32_t sieve_wg_per_cu(const bx_ctx* c) { return c->tile == kTileLarge ? 1u : 2u; }
+
+// One search: plan, buffers and launch shapes.
+struct Job {
+  Segs* s = nullptr;
+  int batch = 0;
+  uint32_t kinds = 3;
   Plan plan;
-  if ((rc = make_plan(c, s.n_keys, sieve_grid, &plan)) != BX_OK) return rc;
-  const uint32_t B1 = 1u << plan.b1bits, B2 = 1u << plan.b2bits, G = plan.group;
-  const uint64_t ngsub = static_cast<uint64_t>(G) * B2;  // sub-buckets of one group
-  const uint64_t n_regions = static_cast<uint64_t>(B1) * sieve_grid;
-  if ((rc = ensure(c, c->l1, n_regions * plan.cap1 * sizeof(Entry))) != BX_OK) return rc;
-  if ((rc = ensure(c, c->l2, ngsub * plan.cap2 * sizeof(Entry))) != BX_OK) return rc;
-  if ((rc = ensure(c, c->cnt1, n_regions * 4ull)) != BX_OK) return rc;
-  if ((rc = ensure(c, c->cnt2, ngsub * 4ull)) != BX_OK) return rc;
+  uint32_t sieve_grid = 0, B1 = 1, B2 = 1, G = 1, cpr = 1;
+  uint64_t ngsub = 1, n_regions = 1, part_grid = 8;
+  uint32_t gmask = 0;
+  uint64_t kmask1 = 0;
+};
+
+int prepare_job(bx_ctx* c, Segs& s, int batch, uint32_t kinds, hipStream_t st, Job* j) {
+  int rc;
+  j->s = &s;
+  j->batch = batch;
+  j->kinds = kinds;
+  j->sieve_grid =
+      static_cast<uint32_t>(std::min<uint64_t>(s.n_segs, static_cast<uint64_t>(c->n_cu) * sieve_wg_per_cu(c)));
+  if ((rc = make_plan(c, s.n_keys, j->sieve_grid, &j->plan)) != BX_OK) return rc;
+  const Plan& plan = j->plan;
+  j->B1 = 1u << plan.b1bits;
+  j->B2 = 1u << plan.b2bits;
+  j->G = plan.group;
+  j->ngsub = static_cast<uint64_t>(j->G) * j->B2;
+  j->n_regions = static_cast<uint64_t>(j->B1) * j->sieve_grid;
+  j->cpr = static_cast<uint32_t>((plan.cap1 + kPartChunk - 1) / kPartChunk);
+  const uint64_t chunks = static_cast<uint64_t>(j->sieve_grid) * j->cpr;  // per bucket
+  j->part_grid = 8ull * ((chunks + (8 / j->G) - 1) / (8 / j->G));
+  if (j->part_grid > 0x7FFFFFFFull) return fail(BX_EINTERNAL, "partition grid too large");
+  j->gmask = batch ? kGrpMask : 0u;
+  j->kmask1 = kM42 | (static_cast<uint64_t>(j->gmask) << kGrpShift);
+  if ((rc = ensure(c, c->l1, j->n_regions * plan.cap1 * sizeof(Entry))) != BX_OK) return rc;
+  if ((rc = ensure(c, c->l2, j->ngsub * plan.cap2 * sizeof(Entry))) != BX_OK) return rc;
+  if ((rc = ensure(c, c->cnt1, j->n_regions * 4ull)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->cnt2, j->ngsub * 4ull)) != BX_OK) return rc;
   if ((rc = ensure(c, c->cand, kCandCap * sizeof(Cand))) != BX_OK) return rc;
   if ((rc = ensure(c, c->out, kCandCap * sizeof(OutPair))) != BX_OK) return rc;
   if ((rc = ensure(c, c->flags, kFlagCount * 4)) != BX_OK) return rc;
-  if ((rc = ensure(c, c->spill, static_cast<size_t>(sieve_grid) * spill_cap_of(c) * 8)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->acc, 8)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->spill, static_cast<size_t>(j->sieve_grid) * spill_cap_of(c) * 8)) != BX_OK) return rc;
   if ((rc = upload_segs(c, s, st)) != BX_OK) return rc;
-  if ((rc = fill_u32(c, c->flags.p, kFlagCount, 0, st)) != BX_OK) return rc;
-  // The join kernel clears every group cursor it reads; they start at zero.
-  if ((rc = fill_u32(c, c->cnt2.p, ngsub, 0, st)) != BX_OK) return rc;
   c->stats.b1_bits = plan.b1bits;
   c->stats.b2_bits = plan.b2bits;
   c->stats.seg_len = c->seg_len;
-  c->stats.tile = kTile;
+  c->stats.tile = static_cast<uint32_t>(c->tile);
+  return BX_OK;
+}
 
-  const uint32_t gmask = batch ? kGrpMask : 0u;
-  const uint64_t kmask1 = kM42 | (static_cast<uint64_t>(gmask) << kGrpShift);
-  // Pass p keeps the keys with pass_hash in [p 2^32 / P, (p+1) 2^32 / P).
-  std::deque<std::pair<uint64_t, uint64_t>> pending;
-  for (uint64_t v = 0; v < plan.passes; ++v)
-    pending.emplace_back((v << 32) / plan.passes, ((v + 1) << 32) / plan.passes);
-  uint32_t cand_before = 0;
+// Counters start at zero; the join kernel clears every group cursor it reads.
+int enqueue_init(bx_ctx* c, const Job& j, hipStream_t st) {
+  int rc;
+  if ((rc = fill_u32(c, c->flags.p, kFlagCount, 0, st)) != BX_OK) return rc;
+  if ((rc = fill_u32(c, c->cnt2.p, j.ngsub, 0, st)) != BX_OK) return rc;
+  if ((rc = fill_u32(c, c->acc.p, 2, 0, st)) != BX_OK) return rc;
+  return BX_OK;
+}
+
+// One pass: keep the keys whose pass hash lies in [ph_lo, ph_hi).  The sieve
+// writes them to first-level regions, then each group of G buckets is split
+// into partitions and joined.
+int enqueue_pass(bx_ctx* c, const Job& j, uint64_t ph_lo, uint64_t ph_hi, hipStream_t st) {
+  const Plan& plan = j.plan;
   uint32_t* d_flags = static_cast<uint32_t*>(c->flags.p);
-  const uint32_t cpr = static_cast<uint32_t>((plan.cap1 + kPartChunk - 1) / kPartChunk);
-  const uint64_t chunks = static_cast<uint64_t>(sieve_grid) * cpr;  // per bucket
-  const uint64_t part_grid = 8ull * ((chunks + (8 / G) - 1) / (8 / G));
-  if (part_grid > 0x7FFFFFFFull) return fail(BX_EINTERNAL, "partition grid too large");
+  SieveParams P = base_sieve_params(c, *j.s);
+  P.batch = j.batch;
+  P.pfilter = !(ph_lo == 0 && ph_hi == (1ull << 32));
+  P.ph_lo = ph_lo;
+  P.ph_hi = ph_hi;
+  P.b1shift = plan.b1bits ? 32 - plan.b1bits : 0;
+  P.b1mask = j.B1 - 1;
+  P.l1 = static_cast<Entry*>(c->l1.p);
+  P.cap1 = plan.cap1;
+  P.cnt1 = static_cast<uint32_t*>(c->cnt1.p);
+  {
+    LaunchTimer t(c, K_SIEVE, st);
+    launch_sieve<MODE_KEYS>(c, P, j.sieve_grid, st);
+  }
+  BX_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_counts, dim3(64), dim3(256), 0, st, static_cast<const uint32_t*>(c->cnt1.p), j.n_regions,
+                     static_cast<unsigned long long*>(c->acc.p));
+  BX_HIP(hipGetLastError());
+  for (uint32_t first = 0; first < j.B1; first += j.G) {
+    PartParams Q;
+    Q.l1 = static_cast<const Entry*>(c->l1.p);
+    Q.cap1 = plan.cap1;
+    Q.cnt1 = static_cast<const uint32_t*>(c->cnt1.p);
+    Q.W = j.sieve_grid;
+    Q.first = first;
+    Q.G = j.G;
+    Q.chunks_per_region = j.cpr;
+    Q.l2 = static_cast<Entry*>(c->l2.p);
+    Q.cap2 = plan.cap2;
+    Q.cnt2 = static_cast<uint32_t*>(c->cnt2.p);
+    Q.b2shift = plan.b2bits ? 32 - plan.b1bits - plan.b2bits : 0;
+    Q.b2mask = j.B2 - 1;
+    Q.gmask = j.gmask;
+    Q.flags = d_flags;
+    {
+      LaunchTimer t(c, K_PART, st);
+      hipLaunchKernelGGL((k_partition<kPartBlock>), dim3(static_cast<uint32_t>(j.part_grid)), dim3(kPartBlock), 0, st, Q);
+    }
+    BX_HIP(hipGetLastError());
+    JoinParams J;
+    J.l2 = static_cast<const Entry*>(c->l2.p);
+    J.cap2 = plan.cap2;
+    J.cnt2 = static_cast<uint32_t*>(c->cnt2.p);
+    J.n_sub = j.ngsub;
+    J.kmask1 = j.kmask1;
+    J.gmask = j.gmask;
+    J.cand = static_cast<Cand*>(c->cand.p);
+    J.cand_cap = kCandCap;
+    J.flags = d_flags;
+    {
+      LaunchTimer t(c, K_JOIN, st);
+      hipLaunchKernelGGL((k_join<kJoinBlock>), dim3(static_cast<uint32_t>(j.ngsub)), dim3(kJoinBlock), 0, st, J);
+    }
+    BX_HIP(hipGetLastError());
+  }
+  return BX_OK;
+}
+
+int enqueue_verify(bx_ctx* c, const Job& j, uint32_t grid, hipStream_t st) {
+  VerifyParams V;
+  V.cand = static_cast<const Cand*>(c->cand.p);
+  V.n_cand = static_cast<const uint32_t*>(c->flags.p) + kFlagCand;
+  V.cand_cap = kCandCap;
+  V.primes = c->d_primes;
+  V.n_primes = static_cast<uint32_t>(c->primes.size());
+  V.queries = static_cast<const Query*>(c->queries.p);
+  V.batch = j.batch;
+  V.kinds = j.kinds;
+  V.out = static_cast<OutPair*>(c->out.p);
+  V.out_cap = kCandCap;
+  V.flags = static_cast<uint32_t*>(c->flags.p);
+  {
+    LaunchTimer t(c, K_VERIFY, st);
+    hipLaunchKernelGGL((k_verify<kVerifyBlock>), dim3(grid), dim3(kVerifyBlock), 0, st, V);
+  }
+  BX_HIP(hipGetLastError());
+  return BX_OK;
+}
+
+int read_flags(bx_ctx* c, uint32_t* fl, hipStream_t st) {
+  BX_HIP(hipMemcpyAsync(fl, c->flags.p, kFlagCount * 4, hipMemcpyDeviceToHost, st));
+  BX_HIP(hipStreamSynchronize(st));
+  return BX_OK;
+}
+
+// Read the verified pairs (flags already read after the verify kernel).
+int collect_pairs(bx_ctx* c, const uint32_t* fl, hipStream_t st, std::vector<OutPair>* result) {
+  if (fl[kFlagSpillOverflow]) return fail(BX_EINTERNAL, "sparse-hit spill buffer overflow");
+  if (fl[kFlagCand] > kCandCap) return fail(BX_EINTERNAL, "candidate buffer overflow");
+  if (fl[kFlagVerifyFail])
+    return fail(BX_EINTERNAL, std::to_string(fl[kFlagVerifyFail]) + " candidate pairs failed exact verification");
+  c->stats.candidates = fl[kFlagCand];
+  const uint32_t n_out = std::min(fl[kFlagOut], kCandCap);
+  c->stats.pairs = n_out;
+  result->resize(n_out);
+  if (n_out) {
+    BX_HIP(hipMemcpyAsync(result->data(), c->out.p, n_out * sizeof(OutPair), hipMemcpyDeviceToHost, st));
+    BX_HIP(hipStreamSynchronize(st));
+  }
+  unsigned long long entries = 0;
+  BX_HIP(hipMemcpyAsync(&entries, c->acc.p, 8, hipMemcpyDeviceToHost, st));
+  BX_HIP(hipStreamSynchronize(st));
+  c->stats.entries = entries;
+  std::sort(result->begin(), result->end(), [](const OutPair& x, const OutPair& y) {
+    if (x.query != y.query) return x.query < y.query;
+    if (x.m != y.m) return x.m < y.m;
+    return x.n < y.n;
+  });
+  return BX_OK;
+}
+
+// Passes run one at a time with a check after each: a pass whose buckets
+// overflow is discarded and run again split in two (one more pass-hash range
+// split), so the result never depends on the bucket sizes.
+int run_passes_checked(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* result) {
+  int rc;
+  if ((rc = enqueue_init(c, j, st)) != BX_OK) return rc;
+  std::deque<std::pair<uint64_t, uint64_t>> pending;
+  for (uint64_t v = 0; v < j.plan.passes; ++v)
+    pending.emplace_back((v << 32) / j.plan.passes, ((v + 1) << 32) / j.plan.passes);
+  uint32_t cand_before = 0;
+  unsigned long long acc_before = 0;
+  uint32_t fl[kFlagCount];
   while (!pending.empty()) {
     const uint64_t ph_lo = pending.front().first, ph_hi = pending.front().second;
     pending.pop_front();
-    SieveParams P = base_sieve_params(c, s);
-    P.batch = batch;
-    P.pfilter = !(ph_lo == 0 && ph_hi == (1ull << 32));
-    P.ph_lo = ph_lo;
-    P.ph_hi = ph_hi;
-    P.b1shift = plan.b1bits ? 32 - plan.b1bits : 0;
-    P.b1mask = B1 - 1;
-    P.l1 = static_cast<Entry*>(c->l1.p);
-    P.cap1 = plan.cap1;
-    P.cnt1 = static_cast<uint32_t*>(c->cnt1.p);
-    {
-      LaunchTimer t(c, K_SIEVE, st);
-      hipLaunchKernelGGL((k_sieve<kTile, kSieveBlock, MODE_KEYS>), dim3(sieve_grid), dim3(kSieveBlock), 0, st, P);
-    }
-    BX_HIP(hipGetLastError());
-    for (uint32_t first = 0; first < B1; first += G) {
-      PartParams Q;
-      Q.l1 = static_cast<const Entry*>(c->l1.p);
-      Q.cap1 = plan.cap1;
-      Q.cnt1 = static_cast<const uint32_t*>(c->cnt1.p);
-      Q.W = sieve_grid;
-      Q.first = first;
-      Q.G = G;
-      Q.chunks_per_region = cpr;
-      Q.l2 = static_cast<Entry*>(c->l2.p);
-      Q.cap2 = plan.cap2;
-      Q.cnt2 = static_cast<uint32_t*>(c->cnt2.p);
-      Q.b2shift = plan.b2bits ? 32 - plan.b1bits - plan.b2bits : 0;
-      Q.b2mask = B2 - 1;
-      Q.gmask = gmask;
-      Q.flags = d_flags;
-      {
-        LaunchTimer t(c, K_PART, st);
-        hipLaunchKernelGGL((k_partition<kPartBlock>), dim3(static_cast<uint32_t>(part_grid)), dim3(kPartBlock), 0, st, Q);
-      }
-      BX_HIP(hipGetLastError());
-      JoinParams J;
-      J.l2 = static_cast<const Entry*>(c->l2.p);
-      J.cap2 = plan.cap2;
-      J.cnt2 = static_cast<uint32_t*>(c->cnt2.p);
-      J.n_sub = ngsub;
-      J.kmask1 = kmask1;
-      J.gmask = gmask;
-      J.cand = static_cast<Cand*>(c->cand.p);
-      J.cand_cap = kCandCap;
-      J.flags = d_flags;
-      {
-        LaunchTimer t(c, K_JOIN, st);
-        hipLaunchKernelGGL((k_join<kJoinBlock>), dim3(static_cast<uint32_t>(ngsub)), dim3(kJoinBlock), 0, st, J);
-      }
-      BX_HIP(hipGetLastError());
-    }
-    uint32_t fl[kFlagCount];
-    BX_HIP(hipMemcpyAsync(fl, d_flags, sizeof(fl), hipMemcpyDeviceToHost, st));
-    BX_HIP(hipStreamSynchronize(st));
+    if ((rc = enqueue_pass(c, j, ph_lo, ph_hi, st)) != BX_OK) return rc;
+    if ((rc = read_flags(c, fl, st)) != BX_OK) return rc;
     c->stats.passes++;
     if (fl[kFlagSpillOverflow]) return fail(BX_EINTERNAL, "sparse-hit spill buffer overflow");
     if (fl[kFlagL1Overflow] || fl[kFlagL2Overflow]) {
-      // Discard this pass's candidates and run it again as two half passes.
       c->stats.retries++;
       if (ph_hi - ph_lo < 2) return fail(BX_EINTERNAL, "bucket overflow on a single pass-hash value");
+      uint32_t* d_flags = static_cast<uint32_t*>(c->flags.p);
       uint32_t z[2] = {0, 0};
       BX_HIP(hipMemcpyAsync(d_flags + kFlagL1Overflow, z, sizeof(z), hipMemcpyHostToDevice, st));
       BX_HIP(hipMemcpyAsync(d_flags + kFlagCand, &cand_before, 4, hipMemcpyHostToDevice, st));
+      BX_HIP(hipMemcpyAsync(c->acc.p, &acc_before, 8, hipMemcpyHostToDevice, st));
       BX_HIP(hipStreamSynchronize(st));
       const uint64_t mid = ph_lo + (ph_hi - ph_lo) / 2;
       pending.emplace_front(mid, ph_hi);
@@ -518,50 +626,96 @@ int run_search(bx_ctx* c, Segs& s, int batch, uint32_t kinds, std::vector<OutPai
       continue;
     }
     cand_before = fl[kFlagCand];
-    std::vector<uint32_t> counts(n_regions);
-    BX_HIP(hipMemcpyAsync(counts.data(), c->cnt1.p, n_regions * 4, hipMemcpyDeviceToHost, st));
+    BX_HIP(hipMemcpyAsync(&acc_before, c->acc.p, 8, hipMemcpyDeviceToHost, st));
     BX_HIP(hipStreamSynchronize(st));
-    for (uint32_t v : counts) c->stats.entries += v;
   }
-  c->stats.integers = s.n_keys;
-  if (cand_before > kCandCap) return fail(BX_EINTERNAL, "candidate buffer overflow");
-  c->stats.candidates = cand_before;
   if (cand_before > 0) {
-    VerifyParams V;
-    V.cand = static_cast<const Cand*>(c->cand.p);
-    V.n_cand = cand_before;
-    V.primes = c->d_primes;
-    V.n_primes = static_cast<uint32_t>(c->primes.size());
-    V.queries = static_cast<const Query*>(c->queries.p);
-    V.batch = batch;
-    V.kinds = kinds;
-    V.out = static_cast<OutPair*>(c->out.p);
-    V.out_cap = kCandCap;
-    V.flags = d_flags;
-    {
-      LaunchTimer t(c, K_VERIFY, st);
-      hipLaunchKernelGGL((k_verify<kVerifyBlock>), dim3(cand_before), dim3(kVerifyBlock), 0, st, V);
-    }
-    BX_HIP(hipGetLastError());
-    uint32_t fl[kFlagCount];
-    BX_HIP(hipMemcpyAsync(fl, d_flags, sizeof(fl), hipMemcpyDeviceToHost, st));
-    BX_HIP(hipStreamSynchronize(st));
-    if (fl[kFlagVerifyFail])
-      return fail(BX_EINTERNAL, std::to_string(fl[kFlagVerifyFail]) + " candidate pairs failed exact verification");
-    const uint32_t n_out = std::min(fl[kFlagOut], kCandCap);
-    c->stats.pairs = n_out;
-    result->resize(n_out);
-    if (n_out) {
-      BX_HIP(hipMemcpyAsync(result->data(), c->out.p, n_out * sizeof(OutPair), hipMemcpyDeviceToHost, st));
-      BX_HIP(hipStreamSynchronize(st));
-    }
+    if (cand_before > kCandCap) return fail(BX_EINTERNAL, "candidate buffer overflow");
+    if ((rc = enqueue_verify(c, j, std::min<uint32_t>(cand_before, kVerifyGrid), st)) != BX_OK) return rc;
   }
-  std::sort(result->begin(), result->end(), [](const OutPair& x, const OutPair& y) {
-    if (x.query != y.query) return x.query < y.query;
-    if (x.m != y.m) return x.m < y.m;
-    return x.n < y.n;
-  });
-  return BX_OK;
+  if ((rc = read_flags(c, fl, st)) != BX_OK) return rc;
+  return collect_pairs(c, fl, st, result);
+}
+
+// All passes and the verification captured into one HIP graph and launched
+// once (instantiated graphs are reused while the launch shapes stay the same).
+// Returns 1 in *redo when a bucket overflowed: the caller then falls back to
+// the checked path.
+int run_passes_graph(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* result, int* redo) {
+  int rc;
+  *redo = 0;
+  // Every launch shape and every buffer address the graph's kernels use.
+  char key[1024];
+  std::snprintf(key, sizeof(key), "%u %llu %u %u %u %u %llu %u %d %u %d %u %p %p %p %p %p %p %p %p %p %p %p %p %p",
+                j.plan.passes, static_cast<unsigned long long>(j.plan.cap1), j.plan.cap2, j.plan.b1bits, j.plan.b2bits,
+                j.G, static_cast<unsigned long long>(j.s->n_segs), static_cast<uint32_t>(j.s->q.size()), j.batch,
+                j.kinds, c->tile, c->seg_len, c->l1.p, c->l2.p, c->spill.p, c->cnt1.p, c->cnt2.p, c->cand.p, c->out.p,
+                c->flags.p, c->acc.p, c->queries.p, c->segpref.p, static_cast<void*>(c->d_pp),
+                static_cast<void*>(c->d_primes));
+  if (!c->graph_exec || c->graph_key != key) {
+    if (c->graph_exec) {
+      BX_HIP(hipGraphExecDestroy(c->graph_exec));
+      c->graph_exec = nullptr;
+    }
+    BX_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    c->capturing = true;
+    rc = enqueue_init(c, j, st);
+    for (uint64_t v = 0; rc == BX_OK && v < j.plan.passes; ++v)
+      rc = enqueue_pass(c, j, (v << 32) / j.plan.passes, ((v + 1) << 32) / j.plan.passes, st);
+    if (rc == BX_OK) rc = enqueue_verify(c, j, kVerifyGrid, st);
+    c->capturing = false;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &g);
+    if (rc != BX_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    BX_HIP(e);
+    e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    BX_HIP(e);
+    c->graph_key = key;
+  }
+  hipEvent_t a = get_event(c), b = get_event(c);
+  if (a) BX_HIP(hipEventRecord(a, st));
+  BX_HIP(hipGraphLaunch(c->graph_exec, st));
+  if (b) BX_HIP(hipEventRecord(b, st));
+  uint32_t fl[kFlagCount];
+  if ((rc = read_flags(c, fl, st)) != BX_OK) return rc;
+  if (a && b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) == hipSuccess) c->stats.graph_ms += ms;
+  }
+  if (a) c->ev_free.push_back(a);
+  if (b) c->ev_free.push_back(b);
+  c->stats.passes += j.plan.passes;
+  if (fl[kFlagL1Overflow] || fl[kFlagL2Overflow]) {
+    *redo = 1;
+    return BX_OK;
+  }
+  return collect_pairs(c, fl, st, result);
+}
+
+// The hash-partitioned exact join over all queries of `s`.
+int run_search(bx_ctx* c, Segs& s, int batch, uint32_t kinds, std::vector<OutPair>* result, bool use_graph) {
+  hipStream_t st = c->stream;
+  result->clear();
+  int rc = order_after_last(c, st);
+  if (rc != BX_OK) return rc;
+  rc = mark_done(c, st);  // host-synchronous from here on: the call drains st
+  if (rc != BX_OK) return rc;
+  make_segs(c, &s);
+  if (s.n_segs == 0) return BX_OK;
+  Job j;
+  if ((rc = prepare_job(c, s, batch, kinds, st, &j)) != BX_OK) return rc;
+  c->stats.integers = s.n_keys;
+  if (use_graph) {
+    int redo = 0;
+    if ((rc = run_passes_graph(c, j, st, result, &redo)) != BX_OK) return rc;
+    if (!redo) return BX_OK;
+    c->stats.retries++;
+  }
+  return run_passes_checked(c, j, st, result);
 }
 
 int to_pairs(const std::vector<OutPair>& v, bx_pair** out, size_t* count) {
@@ -583,7 +737,7 @@ int radicals_into(bx_ctx* c, uint64_t lo, uint64_t hi, uint64_t* dev_out, hipStr
   int rc;
   if ((rc = upload_segs(c, s, st)) != BX_OK) return rc;
   if ((rc = ensure(c, c->flags, kFlagCount * 4)) != BX_OK) return rc;
-  const uint32_t grid = static_cast<uint32_t>(std::min<uint64_t>(s.n_segs, 4ull * c->n_cu));
+  const uint32_t grid = static_cast<uint32_t>(std::min<uint64_t>(s.n_segs, 2ull * sieve_wg_per_cu(c) * c->n_cu));
   if ((rc = ensure(c, c->spill, static_cast<size_t>(grid) * spill_cap_of(c) * 8)) != BX_OK) return rc;
   if ((rc = fill_u32(c, c->flags.p, kFlagCount, 0, st)) != BX_OK) return rc;
   SieveParams P = base_sieve_params(c, s);
@@ -592,7 +746,7 @@ int radicals_into(bx_ctx* c, uint64_t lo, uint64_t hi, uint64_t* dev_out, hipStr
   P.rad_hi = hi;
   {
     LaunchTimer t(c, K_RAD, st);
-    hipLaunchKernelGGL((k_sieve<kTile, kSieveBlock, MODE_RAD>), dim3(grid), dim3(kSieveBlock), 0, st, P);
+    launch_sieve<MODE_RAD>(c, P, grid, st);
   }
   BX_HIP(hipGetLastError());
   return BX_OK;
@@ -694,7 +848,7 @@ void serve_worker(bx_ctx::Server* S, int lane) {
     {
       std::lock_guard<std::mutex> lk(c->mu);
       reset_stats(c);
-      rc = run_search(c, s, 1, BX_BOTH, &res);
+      rc = run_search(c, s, 1, BX_BOTH, &res, c->graph_batch != 0);
       (void)hipStreamSynchronize(c->stream);
       collect_timings(c);
     }
@@ -736,6 +890,9 @@ int bx_create(bx_ctx** out, int device, uint64_t hi_max, uint64_t hbm_budget_byt
   hipDeviceProp_t prop;
   BX_HIP(hipGetDeviceProperties(&prop, device));
   c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  c->arch = prop.gcnArchName;
+  const size_t colon = c->arch.find(':');
+  if (colon != std::string::npos) c->arch.resize(colon);
   BX_HIP(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
   c->stream = c->own_stream;
   size_t free_b = 0, total_b = 0;
@@ -753,11 +910,13 @@ void bx_destroy(bx_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (DevBuf* b : {&c->l1, &c->l2, &c->cnt1, &c->cnt2, &c->cand, &c->out, &c->flags, &c->spill, &c->queries,
-                    &c->segpref, &c->rad})
+                    &c->segpref, &c->rad, &c->acc})
     free_buf(*b);
   if (c->d_primes) (void)hipFree(c->d_primes);
   if (c->d_pp) (void)hipFree(c->d_pp);
-  if (c->d_dense) (void)hipFree(c->d_dense);
+  for (DenseTab* d : c->d_dense)
+    if (d) (void)hipFree(d);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   reset_stats(c);
   for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
   if (c->last_done) (void)hipEventDestroy(c->last_done);
@@ -781,12 +940,18 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
     c->force_passes = static_cast<int>(v);
   } else if (n == "seg_len") {
     if (v == 0) v = kDefaultSegLen;
-    if (v < kTile || v % kTile || v > (1 << 24)) return fail(BX_EINVAL, "seg_len must be a multiple of the tile in [tile, 2^24]");
+    if (v < kTileLarge || v % kTileLarge || v > (1 << 24))
+      return fail(BX_EINVAL, "seg_len must be a multiple of 4096 in [4096, 2^24]");
     c->seg_len = static_cast<uint32_t>(v);
   } else if (n == "timing") {
     c->timing = v != 0;
   } else if (n == "verify") {
     c->verify = v != 0;
+  } else if (n == "tile") {
+    if (v != 0 && v != kTileSmall && v != kTileLarge) return fail(BX_EINVAL, "tile must be 0, 2048 or 4096");
+    c->tile = v == 0 ? kTileSmall : static_cast<int>(v);
+  } else if (n == "graph") {
+    c->graph_batch = v != 0;
   } else if (n == "group") {
     if (v != 0 && v != 1 && v != 2 && v != 4 && v != 8) return fail(BX_EINVAL, "group must be 0, 1, 2, 4 or 8");
     c->force_group = static_cast<int>(v);
@@ -867,7 +1032,7 @@ int bx_search_range(bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds, bx_pair**
   Segs s;
   s.q.push_back(Query{a, b});
   std::vector<OutPair> res;
-  rc = run_search(c, s, 0, kinds, &res);
+  rc = run_search(c, s, 0, kinds, &res, false);
   (void)hipStreamSynchronize(c->stream);
   collect_timings(c);
   c->stats.total_ms = (now_s() - t0) * 1e3;
@@ -904,7 +1069,7 @@ int bx_search_batch(bx_ctx* c, const uint64_t* a, const uint64_t* b, size_t q, u
   }
   BX_HIP(hipSetDevice(c->device));
   std::vector<OutPair> res;
-  int rc = run_search(c, s, 1, kinds, &res);
+  int rc = run_search(c, s, 1, kinds, &res, c->graph_batch != 0);
   (void)hipStreamSynchronize(c->stream);
   collect_timings(c);
   c->stats.total_ms = (now_s() - t0) * 1e3;
@@ -936,7 +1101,9 @@ int bx_serve_start(bx_ctx* c, uint64_t budget_bytes, int max_inflight) {
       return rc;
     }
     lane->seg_len = c->seg_len;
+    lane->tile = c->tile;
     lane->timing = 0;
+    lane->graph_batch = 0;  // batch shapes change from batch to batch: no graph reuse
     S->lanes.push_back(lane);
   }
   bx_ctx::Server* raw = S.get();
@@ -1015,6 +1182,116 @@ int bx_take(bx_ctx* c, uint64_t ticket, bx_pair** out, size_t* count, double* t_
   if (t_done) *t_done = r->t_done;
   if (r->rc != BX_OK) return fail(r->rc, "request failed");
   return to_pairs(r->pairs, out, count);
+}
+
+int bx_autotune(bx_ctx* c, const uint64_t* a, const uint64_t* b, size_t q, int reps, const char* path) {
+  if (!c || !a || !b || q == 0 || reps < 1) return fail(BX_EINVAL, "bad autotune arguments");
+  if (q > kMaxQueries) return fail(BX_EINVAL, "at most 32768 queries per batch");
+  const int saved_tile = c->tile, saved_group = c->force_group;
+  const uint32_t saved_seg = c->seg_len;
+  struct Best {
+    int tile = kTileSmall, group = 8;
+    uint32_t seg = kDefaultSegLen;
+    double ms = 1e300;
+  } best;
+  std::vector<OutPair> ref;
+  bool have_ref = false;
+  int rc = BX_OK;
+  for (int tile : {kTileSmall, kTileLarge}) {
+    for (uint32_t seg : {1u << 15, 1u << 16, 1u << 17, 1u << 18, 1u << 19}) {
+      for (int group : {2, 4, 8}) {
+        double t_best = 1e300;
+        for (int r = 0; r <= reps && rc == BX_OK; ++r) {
+          std::lock_guard<std::mutex> lk(c->mu);
+          c->tile = tile;
+          c->seg_len = seg;
+          c->force_group = group;
+          reset_stats(c);
+          Segs s;
+          for (size_t i = 0; i < q; ++i) {
+            const uint64_t ai = a[i] == 0 ? 1 : a[i];
+            uint64_t bi = b[i] < ai ? ai : b[i];
+            if (bi - ai > kMaxQueryLen) rc = fail(BX_EINVAL, "query longer than 2^28");
+            if (bi > ai + 1 && rc == BX_OK) rc = check_query(c, ai, bi);
+            if (bi <= ai + 1) bi = ai;
+            s.q.push_back(Query{ai, bi});
+          }
+          if (rc != BX_OK) break;
+          BX_HIP(hipSetDevice(c->device));
+          std::vector<OutPair> res;
+          const double t0 = now_s();
+          rc = run_search(c, s, 1, BX_BOTH, &res, c->graph_batch != 0);
+          (void)hipStreamSynchronize(c->stream);
+          const double ms = (now_s() - t0) * 1e3;
+          collect_timings(c);
+          if (rc != BX_OK) break;
+          if (!have_ref) {
+            ref = res;
+            have_ref = true;
+          } else if (res.size() != ref.size() ||
+                     !std::equal(res.begin(), res.end(), ref.begin(), [](const OutPair& x, const OutPair& y) {
+                       return x.m == y.m && x.n == y.n && x.kind == y.kind && x.query == y.query;
+                     })) {
+            rc = fail(BX_EINTERNAL, "autotune: results differ between settings");
+          }
+          if (r > 0) t_best = std::min(t_best, ms);
+        }
+        if (rc != BX_OK) break;
+        if (t_best < best.ms) best = Best{tile, group, seg, t_best};
+      }
+      if (rc != BX_OK) break;
+    }
+    if (rc != BX_OK) break;
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (rc != BX_OK) {
+    c->tile = saved_tile;
+    c->seg_len = saved_seg;
+    c->force_group = saved_group;
+    return rc;
+  }
+  c->tile = best.tile;
+  c->seg_len = best.seg;
+  c->force_group = best.group;
+  if (path) {
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(BX_EDEVICE, std::string("cannot write ") + path);
+    std::fprintf(f, "{\"arch\": \"%s\", \"tile\": %d, \"seg_len\": %u, \"group\": %d, \"ms\": %.3f}\n", c->arch.c_str(),
+                 best.tile, best.seg, best.group, best.ms);
+    std::fclose(f);
+  }
+  return BX_OK;
+}
+
+int bx_load_tuning(bx_ctx* c, const char* path) {
+  if (!c || !path) return fail(BX_EINVAL, "NULL argument");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(BX_EINVAL, std::string("cannot read ") + path);
+  char buf[1024] = {0};
+  const size_t n = std::fread(buf, 1, sizeof(buf) - 1, f);
+  std::fclose(f);
+  buf[n] = 0;
+  const std::string t(buf);
+  auto field = [&](const char* name, long long* v) {
+    const size_t k = t.find(std::string("\"") + name + "\"");
+    if (k == std::string::npos) return false;
+    const size_t colon = t.find(':', k);
+    if (colon == std::string::npos) return false;
+    return std::sscanf(t.c_str() + colon + 1, " %lld", v) == 1;
+  };
+  const size_t ka = t.find("\"arch\"");
+  if (ka != std::string::npos) {
+    const size_t q1 = t.find('"', t.find(':', ka));
+    const size_t q2 = q1 == std::string::npos ? q1 : t.find('"', q1 + 1);
+    if (q1 != std::string::npos && q2 != std::string::npos && t.substr(q1 + 1, q2 - q1 - 1) != c->arch) return BX_OK;
+  }
+  long long tile = 0, seg = 0, group = 0;
+  if (!field("tile", &tile) || !field("seg_len", &seg) || !field("group", &group))
+    return fail(BX_EINVAL, std::string("malformed tuning file ") + path);
+  int rc;
+  if ((rc = bx_set_option(c, "tile", tile)) != BX_OK) return rc;
+  if ((rc = bx_set_option(c, "seg_len", seg)) != BX_OK) return rc;
+  return bx_set_option(c, "group", group);
 }
 
 double bx_now(void) { return now_s(); }

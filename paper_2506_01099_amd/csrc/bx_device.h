@@ -50,7 +50,7 @@ struct OutPair {
 // spreads their multiples over the threads of a workgroup: slot t belongs to
 // power slot_d[t] and is its (t - prefix[d])-th multiple in the tile.
 constexpr int kDenseMax = 64;
-constexpr int kDenseSlotMax = 1024;
+constexpr int kDenseSlotMax = 1152;
 struct DenseTab {
   uint32_t n, nslots;
   uint32_t q[kDenseMax], p[kDenseMax], pinv[kDenseMax], prefix[kDenseMax];

@@ -462,7 +462,8 @@ __global__ __launch_bounds__(BLOCK) void k_join(JoinParams P) {
 
 struct VerifyParams {
   const Cand* cand;
-  uint32_t n_cand;
+  const uint32_t* n_cand;  // candidate count, read on the device (graph replays)
+  uint32_t cand_cap;
   const uint32_t* primes;  // all primes <= sqrt(hi_max), ascending
   uint32_t n_primes;
   const Query* queries;
@@ -480,8 +481,9 @@ template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_verify(VerifyParams P) {
   __shared__ uint64_t red_r[4][BLOCK], red_s[4][BLOCK];
   const int tid = threadIdx.x;
-  const uint32_t c = blockIdx.x;
-  if (c >= P.n_cand) return;
+  const uint32_t n_cand = min(*P.n_cand, P.cand_cap);
+  for (uint32_t c = blockIdx.x; c < n_cand; c += gridDim.x) {
+  __syncthreads();
   const Cand cd = P.cand[c];
   const uint32_t qa_idx = entry_grp(cd.a, P.batch ? kGrpMask : 0u);
   const uint64_t off = P.batch ? P.queries[qa_idx].a : 0ull;
@@ -549,6 +551,16 @@ __global__ __launch_bounds__(BLOCK) void k_verify(VerifyParams P) {
       }
     }
   }
+  }
+}
+
+// Sum of n counters into *acc (entries written by a pass).
+__global__ void k_sum_counts(const uint32_t* cnt, uint64_t n, unsigned long long* acc) {
+  uint64_t s = 0;
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    s += cnt[i];
+  if (s) atomicAdd(acc, static_cast<unsigned long long>(s));
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {

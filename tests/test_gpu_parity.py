@@ -300,3 +300,67 @@ def test_served_alone_equals_in_mix(ctx):
         pairs, ts, td = results[t]
         assert pairs == want
         assert td >= ts
+
+
+# --- graph capture, tiles, autotuner -----------------------------------------------------
+
+def test_batch_graph_replays_match_eager(ctx):
+    """The captured batch graph, replayed with eager work and syncs in between, equals the eager path."""
+    import torch
+
+    from paper_2506_01099_amd.inputs import batched_queries, planted_queries
+
+    a1, b1 = planted_queries()
+    a2, b2 = batched_queries(n=64, seed=11, log2_min=10, log2_max=16, a_bits=36)
+    a = np.concatenate([a1, a2])
+    b = np.concatenate([b1, b2])
+    ctx.set_option("graph", 0)
+    try:
+        eager = ctx.search_batch(a, b)
+    finally:
+        ctx.set_option("graph", 1)
+    for rep in range(4):
+        got = ctx.search_batch(a, b)
+        st = ctx.stats()
+        assert got == eager, rep
+        assert st["graph_ms"] > 0
+        # eager work between replays
+        assert ctx.search(1 << 16) == oracle.search(1 << 16)
+        torch.cuda.synchronize()
+    for i in range(a1.size):
+        assert eager[i] == oracle.search_range(int(a1[i]), int(b1[i]))
+
+
+@pytest.mark.parametrize("tile", [2048, 4096])
+def test_tile_invariance(ctx, tile):
+    ctx.set_option("tile", tile)
+    try:
+        got = ctx.search(1 << 22)
+        rad = ctx.radical_segment((1 << 40) - 70000, (1 << 40) + 70000)
+        st = ctx.stats()
+    finally:
+        ctx.set_option("tile", 0)
+    assert got == theorem1_pairs(1 << 22)
+    assert np.array_equal(rad, oracle.radicals((1 << 40) - 70000, (1 << 40) + 70000))
+
+
+def test_autotune_and_load(ctx, tmp_path):
+    from paper_2506_01099_amd import Benelux
+    from paper_2506_01099_amd.inputs import planted_queries
+
+    a, b = planted_queries()
+    path = tmp_path / "tune.json"
+    with Benelux(device=0) as t:
+        t.autotune(a, b, reps=1, path=path)
+        text = path.read_text()
+        assert '"tile"' in text and '"seg_len"' in text and '"group"' in text
+        got = t.search_batch(a, b)
+    for i in range(a.size):
+        assert got[i] == oracle.search_range(int(a[i]), int(b[i]))
+    ctx.load_tuning(path)
+    try:
+        assert ctx.search(1 << 20) == oracle.search(1 << 20)
+    finally:
+        ctx.set_option("tile", 0)
+        ctx.set_option("seg_len", 0)
+        ctx.set_option("group", 0)
