@@ -37,8 +37,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--log2n", type=int, default=36)
-    ap.add_argument("--batched", action="store_true", help="also time the 4096-query batched workload")
-    ap.add_argument("--served", type=float, default=0.0, help="also run the served trace for this many seconds")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 4096-query batched workload")
+    ap.add_argument("--served", type=float, default=10.0,
+                    help="seconds of the served trace to replay (0 = skip)")
+    ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2506_01099_amd", "tuning_gfx950.json"),
+                    help="autotuner result to load for the batched and served runs (if present)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-sample-log2", type=int, default=22)
     return ap.parse_args()
@@ -164,9 +167,15 @@ def main():
         "kernel_ms_per_step": {k: v / args.steps for k, v in agg["kernel_ms"].items()},
         "step_seconds": per_step,
     }
-    if args.batched:
+    if not args.no_batched or args.served > 0:
+        if os.path.exists(args.tuning):
+            bx.load_tuning(args.tuning)
+            line["tuning"] = open(args.tuning).read().strip()
+    if not args.no_batched:
+        log("batched workload ...")
         line["batched"] = run_batched(bx)
     if args.served > 0:
+        log(f"served trace ({args.served:.0f} s) ...")
         line["served"] = run_served(bx, args.served)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")

@@ -23,7 +23,6 @@ constexpr int MODE_RAD = 0;
 constexpr int MODE_KEYS = 1;
 
 constexpr int kHitCap = 1024;      // sparse-hit list held in LDS per segment
-constexpr int kStageCap = 2048;    // staged entries per workgroup before a flush
 constexpr int kB1Max = 1024;       // first partition fan-out
 constexpr int kB2Max = 2048;       // second partition fan-out
 constexpr int kPartChunk = 4096;   // entries per workgroup in k_partition
@@ -61,16 +60,17 @@ template <int T, int BLOCK>
 struct SieveShCommon {
   uint64_t tile[T + 1];
   uint64_t hits[kHitCap];
-  uint32_t dres[kDenseMax], doff[kDenseMax], dq[kDenseMax], dp[kDenseMax], dpinv[kDenseMax], dprefix[kDenseMax];
-  uint8_t slot_d[kDenseSlotMax];
+  uint32_t dres[kDenseMax], doff[kDenseMax], dq[kDenseMax];
   uint32_t hit_n, n_act, stage_n, pad;
   uint32_t wsum[BLOCK / 64];
 };
 
+// The stage holds one tile's worth of entries (a flush happens before a tile
+// whose entries might not fit).
 template <int T, int BLOCK>
 struct SieveShKeys : SieveShCommon<T, BLOCK> {
-  Entry stage[kStageCap];
-  uint16_t sb[kStageCap], perm[kStageCap];
+  Entry stage[T];
+  uint16_t sb[T], perm[T];
   uint32_t cnt[kB1Max], gofs[kB1Max], lcur[kB1Max];
 };
 
@@ -157,17 +157,35 @@ __device__ void flush_stage(SieveShKeys<T, BLOCK>& sh, const SieveParams& P) {
 template <int T, int BLOCK, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
   using Sh = typename SieveShSel<T, BLOCK, MODE>::type;
+  static_assert(T % BLOCK == 0 && T <= 65536, "tile shape");
+  constexpr int ITER = T / BLOCK;                                     // keys per thread per tile
+  constexpr int SLOTS = (kDenseSlotMax + BLOCK - 1) / BLOCK;          // dense slots per thread
   __shared__ Sh sh;
   const int tid = threadIdx.x;
   const DenseTab* D = P.dense;
   const uint32_t nd = D->n, nslots = D->nslots;
-  for (uint32_t i = tid; i < nd; i += BLOCK) {
-    sh.dq[i] = D->q[i];
-    sh.dp[i] = D->p[i];
-    sh.dpinv[i] = D->pinv[i];
-    sh.dprefix[i] = D->prefix[i];
+  for (uint32_t i = tid; i < nd; i += BLOCK) sh.dq[i] = D->q[i];
+  // The dense schedule is the same for every tile: each thread keeps its
+  // slots (power index, multiple index, q, p, p^-1) in registers.
+  uint32_t sd[SLOTS], sj[SLOTS], sq[SLOTS], sp[SLOTS], spinv[SLOTS];
+#pragma unroll
+  for (int k = 0; k < SLOTS; ++k) {
+    const uint32_t t = tid + k * BLOCK;
+    if (t < nslots) {
+      const uint32_t d = D->slot_d[t];
+      sd[k] = d;
+      sj[k] = t - D->prefix[d];
+      sq[k] = D->q[d];
+      sp[k] = D->p[d];
+      spinv[k] = D->pinv[d];
+    } else {
+      sd[k] = 0;
+      sj[k] = 0;
+      sq[k] = 0;  // no slot
+      sp[k] = 1;
+      spinv[k] = 1;
+    }
   }
-  for (uint32_t i = tid; i < nslots; i += BLOCK) sh.slot_d[i] = D->slot_d[i];
   if (tid == 0) sh.stage_n = 0;
   if constexpr (MODE == MODE_KEYS) {
     for (uint32_t b = tid; b < kB1Max; b += BLOCK) sh.lcur[b] = 0;
@@ -238,10 +256,11 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
       }
       __syncthreads();
       // Dense odd prime powers: divide r by p at every multiple of q = p^k.
-      for (uint32_t t = tid; t < nslots; t += BLOCK) {
-        const uint32_t d = sh.slot_d[t];
-        const uint32_t pos = sh.doff[d] + (t - sh.dprefix[d]) * sh.dq[d];
-        if (pos <= cnt) lds_div(&sh.tile[pos], sh.dp[d], sh.dpinv[d]);
+#pragma unroll
+      for (int k = 0; k < SLOTS; ++k) {
+        if (sq[k] == 0) continue;
+        const uint32_t pos = sh.doff[sd[k]] + sj[k] * sq[k];
+        if (pos <= cnt) lds_div(&sh.tile[pos], sp[k], spinv[k]);
       }
       // Sparse hits of this tile.
       for (uint32_t h = tid; h < nh; h += BLOCK) {
@@ -260,38 +279,52 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
           if (x >= P.rad_lo && x < P.rad_hi) P.rad_out[x - P.rad_lo] = sh.tile[i];
         }
       } else {
-        if (sh.stage_n + cnt > static_cast<uint32_t>(kStageCap)) flush_stage<T, BLOCK>(sh, P);
+        if (sh.stage_n + cnt > static_cast<uint32_t>(T)) flush_stage<T, BLOCK>(sh, P);
         const uint32_t grp = P.batch ? qi : 0u;
-        for (uint32_t i0 = 0; i0 < cnt; i0 += BLOCK) {
-          const uint32_t i = i0 + tid;
-          bool keep = false;
-          Entry en{0, 0};
-          uint32_t b1 = 0;
+        // Keys of this thread's ITER integers, then one stage reservation per
+        // wave: ballots give every lane its rank, lane 0 reserves the total.
+        bool keep[ITER];
+        Entry en[ITER];
+        uint32_t b1v[ITER];
+        uint64_t mask[ITER];
+        uint32_t total = 0;
+#pragma unroll
+        for (int it = 0; it < ITER; ++it) {
+          const uint32_t i = it * BLOCK + tid;
+          keep[it] = false;
+          b1v[it] = 0;
           if (i < cnt) {
             const uint64_t a = sh.tile[i], b = sh.tile[i + 1];
             const uint64_t klo = a < b ? a : b, khi = a < b ? b : a;
             if (P.pfilter) {
               const uint64_t ph = pass_hash(klo, khi, grp);
-              keep = ph >= P.ph_lo && ph < P.ph_hi;
+              keep[it] = ph >= P.ph_lo && ph < P.ph_hi;
             } else {
-              keep = true;
+              keep[it] = true;
             }
-            if (keep) {
-              b1 = (key_hash(klo, khi, grp) >> P.b1shift) & P.b1mask;
+            if (keep[it]) {
+              b1v[it] = (key_hash(klo, khi, grp) >> P.b1shift) & P.b1mask;
               const uint64_t x = x0 + i;
-              en = make_entry(klo, khi, P.batch ? x - qa : x, grp, a > b ? 1u : 0u);
+              en[it] = make_entry(klo, khi, P.batch ? x - qa : x, grp, a > b ? 1u : 0u);
             }
           }
-          const uint64_t mask = __ballot(keep);
-          const uint32_t nk = __popcll(mask);
+          mask[it] = __ballot(keep[it]);
+          total += __popcll(mask[it]);
+        }
+        if (total) {
           const uint32_t lane = lane_id();
-          const uint32_t rk = __popcll(mask & ((1ull << lane) - 1ull));
+          const uint64_t below = (1ull << lane) - 1ull;
           uint32_t wb = 0;
-          if (lane == 0 && nk) wb = atomicAdd(&sh.stage_n, nk);
-          wb = __shfl(wb, 0, 64);
-          if (keep) {
-            sh.stage[wb + rk] = en;
-            sh.sb[wb + rk] = static_cast<uint16_t>(b1);
+          if (lane == 0) wb = atomicAdd(&sh.stage_n, total);
+          wb = __builtin_amdgcn_readfirstlane(wb);
+#pragma unroll
+          for (int it = 0; it < ITER; ++it) {
+            if (keep[it]) {
+              const uint32_t pos = wb + __popcll(mask[it] & below);
+              sh.stage[pos] = en[it];
+              sh.sb[pos] = static_cast<uint16_t>(b1v[it]);
+            }
+            wb += __popcll(mask[it]);
           }
         }
       }
