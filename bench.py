@@ -25,6 +25,9 @@ VALU_PEAK_INT_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes/clk x 2.4 GHz (32-bit
 # factor 2, the odd prime-power divisions at 0.273 per integer, canonical key, hash, pass test).
 SIEVE_OPS_PER_INT = 27.0
 ENTRY_BYTES = 16
+CALIB_BYTES = 4 << 30
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plain_2p36.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2506_01099_amd", "csrc", f) for f in ("bx_kernels.h", "bx_device.h")]
 
 
 def log(msg):
@@ -43,6 +46,10 @@ def parse():
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2506_01099_amd", "tuning_gfx950.json"),
                     help="autotuner result to load for the batched and served runs (if present)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--calib", action="store_true",
+                    help="first copy 4 GiB with a plain copy kernel (reference for HBM counters)")
+    ap.add_argument("--parse-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into " + TRAFFIC_FILE)
     ap.add_argument("--cpu-sample-log2", type=int, default=22)
     return ap.parse_args()
 
@@ -60,6 +67,80 @@ def cpu_baseline(N, log2_sample):
             "sample": f"oracle.search_range over x in [{a}, {N + 1}) ({N + 1 - a} integers at magnitude 2^{int(math.log2(N))}); "
                       f"radicals {t_rad:.2f} s on {threads} threads, hash-map join {t_join:.2f} s on 1 thread",
             "seconds": dt}
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def calib_copy():
+    """A plain device-to-device copy of CALIB_BYTES (reference kernel for the counters)."""
+    import torch
+
+    src = torch.empty(CALIB_BYTES // 8, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def parse_counters(fetch_dir, write_dir):
+    """Per-kernel HBM bytes per launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch), scaled
+    by the factor that maps the calibration copy's counters onto its known bytes."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        per = {}
+        for f in files:
+            for r in csv.DictReader(open(f)):
+                if r.get("Counter_Name") != counter:
+                    continue
+                name = r["Kernel_Name"]
+                per.setdefault(name, []).append(float(r["Counter_Value"]))
+        return per
+
+    fetch, write = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+
+    def pick(per, key):
+        vals = [v for k, lst in per.items() if key in k for v in lst]
+        return sum(vals) / len(vals) if vals else None
+
+    copy_key = "copy"  # torch's elementwise copy kernel
+    f_copy = max((max(l) for k, l in fetch.items() if copy_key in k.lower()), default=None)
+    w_copy = max((max(l) for k, l in write.items() if copy_key in k.lower()), default=None)
+    f_scale = CALIB_BYTES / (f_copy * 1024) if f_copy else None
+    w_scale = CALIB_BYTES / (w_copy * 1024) if w_copy else None
+    out = {"source_hash": kernel_source_hash(), "calib_bytes": CALIB_BYTES,
+           "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
+    for k, key in (("sieve", "k_sieve"), ("partition", "k_partition"), ("join", "k_join")):
+        f, w = pick(fetch, key), pick(write, key)
+        if f is None or w is None or not f_scale or not w_scale:
+            continue
+        out["kernels"][k] = {"fetch_bytes_per_launch": f * 1024 * f_scale,
+                             "write_bytes_per_launch": w * 1024 * w_scale,
+                             "launches": len([v for kk, l in fetch.items() if key in kk for v in l])}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
+def load_traffic():
+    """Measured HBM bytes per launch, or None when the kernels changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return {}
+    t = json.load(open(TRAFFIC_FILE))
+    if t.get("source_hash") != kernel_source_hash():
+        return {}
+    return {k: v["fetch_bytes_per_launch"] + v["write_bytes_per_launch"] for k, v in t.get("kernels", {}).items()}
 
 
 def run_plain(bx, N, steps, warmup):
@@ -89,7 +170,7 @@ def run_plain(bx, N, steps, warmup):
     return pairs, total, per_step, agg
 
 
-def roofline_from(agg, n_keys_per_step, steps):
+def roofline_from(agg, n_keys_per_step, steps, traffic):
     ms = agg["kernel_ms"]
     ln = agg["launches"]
     kinds = {k: ms[k] for k in ("sieve", "partition", "join")}
@@ -101,7 +182,7 @@ def roofline_from(agg, n_keys_per_step, steps):
         ints_per_launch = n_keys_per_step * steps / ln["sieve"]
         ach = SIEVE_OPS_PER_INT * ints_per_launch / (avg_ms * 1e-3) / 1e12
         out["sieve"] = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_INT_OPS / 1e12, "unit": "Tops/s",
-                        "frac": ach / (VALU_PEAK_INT_OPS / 1e12), "traffic": None,
+                        "frac": ach / (VALU_PEAK_INT_OPS / 1e12), "traffic": traffic.get("sieve"),
                         "avg_launch_ms": avg_ms, "integers_per_launch": ints_per_launch}
     # Partition: HBM-bound, 16 B read + 16 B write per entry.
     entries_per_step = n_keys_per_step
@@ -110,14 +191,14 @@ def roofline_from(agg, n_keys_per_step, steps):
         b = 2 * ENTRY_BYTES * entries_per_step * steps / ln["partition"]
         ach = b / (avg_ms * 1e-3) / 1e9
         out["partition"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": avg_ms,
+                            "frac": ach / HBM_PEAK_GBS, "traffic": traffic.get("partition"), "avg_launch_ms": avg_ms,
                             "bytes_per_launch": b}
     if ln["join"]:
         avg_ms = ms["join"] / ln["join"]
         b = ENTRY_BYTES * entries_per_step * steps / ln["join"]
         ach = b / (avg_ms * 1e-3) / 1e9
         out["join"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": avg_ms,
+                       "frac": ach / HBM_PEAK_GBS, "traffic": traffic.get("join"), "avg_launch_ms": avg_ms,
                        "bytes_per_launch": b}
     # The join as a whole (second scatter + LDS join): 32 B per key algorithmic
     # (one 16 B entry written by the sieve, read once), over the join kernels' time.
@@ -131,6 +212,9 @@ def roofline_from(agg, n_keys_per_step, steps):
 
 def main():
     args = parse()
+    if args.parse_counters:
+        parse_counters(*args.parse_counters)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described "
               "in DESIGN.md and is not built", file=sys.stderr)
@@ -140,11 +224,13 @@ def main():
     from paper_2506_01099_amd import Benelux
 
     N = 1 << args.log2n
+    if args.calib:
+        calib_copy()
     bx = Benelux(device=0)
     pairs, total, per_step, agg = run_plain(bx, N, args.steps, args.warmup)
     ms_step = total / args.steps * 1e3
     value = N / (total / args.steps)
-    dominant, roof = roofline_from(agg, N, args.steps)
+    dominant, roof = roofline_from(agg, N, args.steps, load_traffic() if args.log2n == 36 else {})
     line = {
         "metric": "integers sieved+joined/s at N=2^36 (both kinds), %HBM roofline; batched vs plain",
         "value": value,
