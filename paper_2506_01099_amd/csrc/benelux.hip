@@ -305,7 +305,7 @@ uint64_t fixed_bytes(const bx_ctx* c, uint32_t sieve_grid) {
 // the second level only needs a buffer for one group of buckets at a time, so
 // the budget sets P through the first level alone.  Second-level partitions
 // end up near 1600-2400 entries, which one workgroup joins in LDS.
-int make_plan(bx_ctx* c, uint64_t n_keys, uint32_t sieve_grid, Plan* out) {
+int make_plan(bx_ctx* c, uint64_t n_keys, uint64_t share, uint32_t sieve_grid, Plan* out) {
   const uint64_t fixed = fixed_bytes(c, sieve_grid);
   const uint32_t p_first = c->force_passes > 0 ? static_cast<uint32_t>(c->force_passes) : 1;
   const uint32_t p_last = c->force_passes > 0 ? p_first : 4096;
@@ -318,9 +318,11 @@ int make_plan(bx_ctx* c, uint64_t n_keys, uint32_t sieve_grid, Plan* out) {
     if (c->force_b1 >= 0) b1 = static_cast<uint32_t>(c->force_b1);
     p.b1bits = b1;
     const double bucket = n_pass / std::ldexp(1.0, static_cast<int>(b1));
-    // Each sieve workgroup owns one region per bucket (no atomics); its share
-    // of a bucket is bucket / W entries, plus slack.
-    p.cap1 = round_up(static_cast<uint64_t>(std::ceil(bucket / W * 1.05)) + 256, 64);
+    // Each sieve workgroup owns one region per bucket (no atomics); it holds
+    // that workgroup's integers of the bucket and pass, plus slack.
+    const double region = static_cast<double>(share) / P / std::ldexp(1.0, static_cast<int>(b1));
+    p.cap1 = round_up(static_cast<uint64_t>(std::ceil(region * 1.05)) + 256, 64);
+    (void)W;
     // Partitions of at most ~7.4k entries (one LDS join chunk holds 8192).
     uint32_t b2 = bucket * 1.03 > 6500.0 ? ceil_log2(bucket * 1.03 / 6500.0) : 0;
     if (c->force_b2 >= 0) b2 = static_cast<uint32_t>(c->force_b2);
@@ -354,6 +356,43 @@ struct Segs {
   std::vector<uint64_t> prefix;
   uint64_t n_segs = 0, n_keys = 0;
 };
+
+// Largest number of integers any of W sieve workgroups processes (segment s
+// goes to workgroup s mod W): it sizes the workgroup-private regions.
+uint64_t max_share(const bx_ctx* c, const Segs& s, uint32_t W) {
+  if (W == 0) return 0;
+  std::vector<int64_t> diff(W + 1, 0);  // full segments per workgroup, as a difference array
+  std::vector<uint64_t> extra(W, 0);    // the shorter last segment of each query
+  for (size_t i = 0; i < s.q.size(); ++i) {
+    const uint64_t L = s.q[i].b > s.q[i].a ? s.q[i].b - s.q[i].a : 0;
+    if (L == 0) continue;
+    const uint64_t nseg = (L + c->seg_len - 1) / c->seg_len, nfull = nseg - 1;
+    const uint64_t first = s.prefix[i] % W;
+    const uint64_t rounds = nfull / W, rem = nfull % W;
+    diff[0] += static_cast<int64_t>(rounds);
+    diff[W] -= static_cast<int64_t>(rounds);
+    if (rem) {
+      const uint64_t end = first + rem;  // [first, end) mod W get one more
+      if (end <= W) {
+        diff[first] += 1;
+        diff[end] -= 1;
+      } else {
+        diff[first] += 1;
+        diff[W] -= 1;
+        diff[0] += 1;
+        diff[end - W] -= 1;
+      }
+    }
+    extra[(s.prefix[i] + nfull) % W] += L - nfull * c->seg_len;
+  }
+  uint64_t best = 0;
+  int64_t run = 0;
+  for (uint32_t w = 0; w < W; ++w) {
+    run += diff[w];
+    best = std::max<uint64_t>(best, static_cast<uint64_t>(run) * c->seg_len + extra[w]);
+  }
+  return best;
+}
 
 void make_segs(const bx_ctx* c, Segs* s) {
   s->prefix.assign(s->q.size() + 1, 0);
@@ -436,7 +475,7 @@ int prepare_job(bx_ctx* c, Segs& s, int batch, uint32_t kinds, hipStream_t st, J
   j->kinds = kinds;
   j->sieve_grid =
       static_cast<uint32_t>(std::min<uint64_t>(s.n_segs, static_cast<uint64_t>(c->n_cu) * sieve_wg_per_cu(c)));
-  if ((rc = make_plan(c, s.n_keys, j->sieve_grid, &j->plan)) != BX_OK) return rc;
+  if ((rc = make_plan(c, s.n_keys, max_share(c, s, j->sieve_grid), j->sieve_grid, &j->plan)) != BX_OK) return rc;
   const Plan& plan = j->plan;
   j->B1 = 1u << plan.b1bits;
   j->B2 = 1u << plan.b2bits;

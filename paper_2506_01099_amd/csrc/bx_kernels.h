@@ -61,7 +61,7 @@ struct SieveShCommon {
   uint64_t tile[T + 1];
   uint64_t hits[kHitCap];
   uint32_t dres[kDenseMax], doff[kDenseMax], dq[kDenseMax];
-  uint32_t hit_n, n_act, stage_n, pad;
+  uint32_t hit_n, n_act, stage_n, tile_kept, tile_pos, pad0, pad1, pad2;
   uint32_t wsum[BLOCK / 64];
 };
 
@@ -186,7 +186,11 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
       spinv[k] = 1;
     }
   }
-  if (tid == 0) sh.stage_n = 0;
+  if (tid == 0) {
+    sh.stage_n = 0;
+    sh.tile_kept = 0;
+    sh.tile_pos = 0;
+  }
   if constexpr (MODE == MODE_KEYS) {
     for (uint32_t b = tid; b < kB1Max; b += BLOCK) sh.lcur[b] = 0;
   }
@@ -279,10 +283,8 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
           if (x >= P.rad_lo && x < P.rad_hi) P.rad_out[x - P.rad_lo] = sh.tile[i];
         }
       } else {
-        if (sh.stage_n + cnt > static_cast<uint32_t>(T)) flush_stage<T, BLOCK>(sh, P);
         const uint32_t grp = P.batch ? qi : 0u;
-        // Keys of this thread's ITER integers, then one stage reservation per
-        // wave: ballots give every lane its rank, lane 0 reserves the total.
+        // Keys of this thread's ITER integers, held in registers ...
         bool keep[ITER];
         Entry en[ITER];
         uint32_t b1v[ITER];
@@ -311,11 +313,21 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
           mask[it] = __ballot(keep[it]);
           total += __popcll(mask[it]);
         }
+        // ... then the tile's kept count decides whether the stage is written
+        // out first: a flush only when the tile's entries would not fit.
+        // stage_n and tile_kept do not change between the barrier and the
+        // decision (stage_n only moves after the end-of-tile barrier), so every
+        // thread takes the same decision.
+        if (total && lane_id() == 0) atomicAdd(&sh.tile_kept, total);
+        __syncthreads();
+        if (sh.stage_n + sh.tile_kept > static_cast<uint32_t>(T)) flush_stage<T, BLOCK>(sh, P);
+        const uint32_t stage_base = sh.stage_n;
+        // Ballots rank every kept lane; lane 0 reserves the wave's stage space.
         if (total) {
           const uint32_t lane = lane_id();
           const uint64_t below = (1ull << lane) - 1ull;
           uint32_t wb = 0;
-          if (lane == 0) wb = atomicAdd(&sh.stage_n, total);
+          if (lane == 0) wb = stage_base + atomicAdd(&sh.tile_pos, total);
           wb = __builtin_amdgcn_readfirstlane(wb);
 #pragma unroll
           for (int it = 0; it < ITER; ++it) {
@@ -329,6 +341,15 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
         }
       }
       __syncthreads();
+      if constexpr (MODE == MODE_KEYS) {
+        // Every thread has read stage_n and tile_kept for this tile (before
+        // the barrier above); the next tile reads them after its own barriers.
+        if (tid == 0) {
+          sh.stage_n += sh.tile_kept;
+          sh.tile_kept = 0;
+          sh.tile_pos = 0;
+        }
+      }
     }
   }
   if constexpr (MODE == MODE_KEYS) {
