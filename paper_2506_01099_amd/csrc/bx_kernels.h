@@ -284,60 +284,59 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
         }
       } else {
         const uint32_t grp = P.batch ? qi : 0u;
-        // Keys of this thread's ITER integers, held in registers ...
+        // 1. The pass test for this thread's ITER integers (cheap, every x).
         bool keep[ITER];
-        Entry en[ITER];
-        uint32_t b1v[ITER];
         uint64_t mask[ITER];
         uint32_t total = 0;
 #pragma unroll
         for (int it = 0; it < ITER; ++it) {
           const uint32_t i = it * BLOCK + tid;
           keep[it] = false;
-          b1v[it] = 0;
           if (i < cnt) {
-            const uint64_t a = sh.tile[i], b = sh.tile[i + 1];
-            const uint64_t klo = a < b ? a : b, khi = a < b ? b : a;
             if (P.pfilter) {
-              const uint64_t ph = pass_hash(klo, khi, grp);
+              const uint64_t a = sh.tile[i], b = sh.tile[i + 1];
+              const uint64_t ph = pass_hash(a < b ? a : b, a < b ? b : a, grp);
               keep[it] = ph >= P.ph_lo && ph < P.ph_hi;
             } else {
               keep[it] = true;
-            }
-            if (keep[it]) {
-              b1v[it] = (key_hash(klo, khi, grp) >> P.b1shift) & P.b1mask;
-              const uint64_t x = x0 + i;
-              en[it] = make_entry(klo, khi, P.batch ? x - qa : x, grp, a > b ? 1u : 0u);
             }
           }
           mask[it] = __ballot(keep[it]);
           total += __popcll(mask[it]);
         }
-        // ... then the tile's kept count decides whether the stage is written
-        // out first: a flush only when the tile's entries would not fit.
-        // stage_n and tile_kept do not change between the barrier and the
-        // decision (stage_n only moves after the end-of-tile barrier), so every
-        // thread takes the same decision.
+        // 2. The tile's kept count decides whether the stage is written out
+        // first: a flush only when the tile's entries would not fit.  stage_n
+        // and tile_kept do not change between the barrier and the decision
+        // (stage_n only moves after the end-of-tile barrier), so every thread
+        // takes the same decision.
         if (total && lane_id() == 0) atomicAdd(&sh.tile_kept, total);
         __syncthreads();
         if (sh.stage_n + sh.tile_kept > static_cast<uint32_t>(T)) flush_stage<T, BLOCK>(sh, P);
-        const uint32_t stage_base = sh.stage_n;
-        // Ballots rank every kept lane; lane 0 reserves the wave's stage space.
+        const uint32_t stage_base = sh.stage_n, kept = sh.tile_kept;
+        // 3. Compaction: ballots rank every kept lane, lane 0 reserves the
+        // wave's part of the list of kept tile positions (the flush's
+        // permutation array, free outside a flush).
         if (total) {
           const uint32_t lane = lane_id();
           const uint64_t below = (1ull << lane) - 1ull;
           uint32_t wb = 0;
-          if (lane == 0) wb = stage_base + atomicAdd(&sh.tile_pos, total);
+          if (lane == 0) wb = atomicAdd(&sh.tile_pos, total);
           wb = __builtin_amdgcn_readfirstlane(wb);
 #pragma unroll
           for (int it = 0; it < ITER; ++it) {
-            if (keep[it]) {
-              const uint32_t pos = wb + __popcll(mask[it] & below);
-              sh.stage[pos] = en[it];
-              sh.sb[pos] = static_cast<uint16_t>(b1v[it]);
-            }
+            if (keep[it]) sh.perm[wb + __popcll(mask[it] & below)] = static_cast<uint16_t>(it * BLOCK + tid);
             wb += __popcll(mask[it]);
           }
+        }
+        __syncthreads();
+        // 4. Entries of the kept integers only, no divergence on the pass test.
+        for (uint32_t k = tid; k < kept; k += BLOCK) {
+          const uint32_t i = sh.perm[k];
+          const uint64_t a = sh.tile[i], b = sh.tile[i + 1];
+          const uint64_t klo = a < b ? a : b, khi = a < b ? b : a;
+          const uint64_t x = x0 + i;
+          sh.stage[stage_base + k] = make_entry(klo, khi, P.batch ? x - qa : x, grp, a > b ? 1u : 0u);
+          sh.sb[stage_base + k] = static_cast<uint16_t>((key_hash(klo, khi, grp) >> P.b1shift) & P.b1mask);
         }
       }
       __syncthreads();
