@@ -326,7 +326,7 @@ int make_plan(bx_ctx* c, uint64_t n_keys, uint64_t share, uint32_t sieve_grid, P
     // Partitions of at most ~7.4k entries (one LDS join chunk holds 8192).
     uint32_t b2 = bucket * 1.03 > 6500.0 ? ceil_log2(bucket * 1.03 / 6500.0) : 0;
     if (c->force_b2 >= 0) b2 = static_cast<uint32_t>(c->force_b2);
-    if (b2 > 11 || b1 + b2 > 32) {
+    if (b2 > 12 || b1 + b2 > 32) {
       if (c->force_passes > 0) return fail(BX_ENOMEM, "forced pass count leaves partitions too large");
       continue;
     }
@@ -998,7 +998,7 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
     if (v > 10) return fail(BX_EINVAL, "b1_bits <= 10");
     c->force_b1 = v == 0 ? -1 : static_cast<int>(v);
   } else if (n == "b2_bits") {
-    if (v > 11) return fail(BX_EINVAL, "b2_bits <= 11");
+    if (v > 12) return fail(BX_EINVAL, "b2_bits <= 12");
     c->force_b2 = v == 0 ? -1 : static_cast<int>(v);
   } else {
     return fail(BX_EINVAL, "unknown option " + n);

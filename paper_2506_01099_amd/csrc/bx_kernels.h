@@ -24,7 +24,7 @@ constexpr int MODE_KEYS = 1;
 
 constexpr int kHitCap = 1024;      // sparse-hit list held in LDS per segment
 constexpr int kB1Max = 1024;       // first partition fan-out
-constexpr int kB2Max = 2048;       // second partition fan-out
+constexpr int kB2Max = 4096;       // second partition fan-out
 constexpr int kPartChunk = 4096;   // entries per workgroup in k_partition
 constexpr int kJoinCap = 8192;     // entries of one LDS join chunk (held in registers)
 constexpr int kJoinSlots = 16384;  // LDS hash-table slots (load <= 0.5)
@@ -464,13 +464,17 @@ __global__ __launch_bounds__(BLOCK) void k_join(JoinParams P) {
   const Entry* src = P.l2 + sbk * P.cap2;
   for (uint32_t i0 = 0; i0 < n; i0 += kJoinCap) {
     const uint32_t m = min(static_cast<uint32_t>(kJoinCap), n - i0);
+    // Table of at least twice the chunk's entries (load <= 0.5), power of two.
+    uint32_t slots = 1024;
+    while (slots < 2 * m && slots < static_cast<uint32_t>(kJoinSlots)) slots <<= 1;
+    const uint32_t smask = slots - 1;
     Entry e[EPT];
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       const uint32_t i = tid + k * BLOCK;
       if (i < m) e[k] = src[i0 + i];
     }
-    for (uint32_t s = tid; s < static_cast<uint32_t>(kJoinSlots); s += BLOCK) table[s] = kEmpty;
+    for (uint32_t s = tid; s < slots; s += BLOCK) table[s] = kEmpty;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
@@ -479,7 +483,7 @@ __global__ __launch_bounds__(BLOCK) void k_join(JoinParams P) {
       const uint64_t k0 = e[k].w0 & kM42, k1 = e[k].w1 & P.kmask1;
       const uint32_t h = key_hash2(k0, e[k].w1 & kM42, entry_grp(e[k], P.gmask));
       const uint32_t mine = (h & ~kIdxMask) | i;
-      uint32_t s = h & (kJoinSlots - 1);
+      uint32_t s = h & smask;
       for (;;) {
         uint32_t v = table[s];
         if (v == kEmpty) {
@@ -490,7 +494,7 @@ __global__ __launch_bounds__(BLOCK) void k_join(JoinParams P) {
           const Entry f = src[i0 + (v & kIdxMask)];
           if ((f.w0 & kM42) == k0 && (f.w1 & P.kmask1) == k1) emit_cand(P, e[k], f);
         }
-        s = (s + 1) & (kJoinSlots - 1);
+        s = (s + 1) & smask;
       }
     }
     __syncthreads();
@@ -498,7 +502,7 @@ __global__ __launch_bounds__(BLOCK) void k_join(JoinParams P) {
       const Entry g = src[jj];
       const uint64_t k0 = g.w0 & kM42, k1 = g.w1 & P.kmask1;
       const uint32_t h = key_hash2(k0, g.w1 & kM42, entry_grp(g, P.gmask));
-      uint32_t s = h & (kJoinSlots - 1);
+      uint32_t s = h & smask;
       for (;;) {
         const uint32_t v = table[s];
         if (v == kEmpty) break;
@@ -506,7 +510,7 @@ __global__ __launch_bounds__(BLOCK) void k_join(JoinParams P) {
           const Entry f = src[i0 + (v & kIdxMask)];
           if ((f.w0 & kM42) == k0 && (f.w1 & P.kmask1) == k1) emit_cand(P, g, f);
         }
-        s = (s + 1) & (kJoinSlots - 1);
+        s = (s + 1) & smask;
       }
     }
     __syncthreads();
