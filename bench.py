@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2506_01099_amd", "tuning_gfx950.json"),
                     help="autotuner result to load for the batched and served runs (if present)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-unpruned", action="store_true",
+                    help="skip the comparison run with the member test off")
     ap.add_argument("--calib", action="store_true",
                     help="first copy 4 GiB with a plain copy kernel (reference for HBM counters)")
     ap.add_argument("--parse-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -170,7 +172,7 @@ def run_plain(bx, N, steps, warmup):
     return pairs, total, per_step, agg
 
 
-def roofline_from(agg, n_keys_per_step, steps, traffic):
+def roofline_from(agg, n_ints_per_step, entries_per_step, steps, traffic):
     ms = agg["kernel_ms"]
     ln = agg["launches"]
     kinds = {k: ms[k] for k in ("sieve", "partition", "join")}
@@ -179,13 +181,13 @@ def roofline_from(agg, n_keys_per_step, steps, traffic):
     # Sieve: ALU-bound.  Algorithmic ops per launch = ops per integer x integers per launch.
     if ln["sieve"]:
         avg_ms = ms["sieve"] / ln["sieve"]
-        ints_per_launch = n_keys_per_step * steps / ln["sieve"]
+        ints_per_launch = n_ints_per_step * steps / ln["sieve"]
         ach = SIEVE_OPS_PER_INT * ints_per_launch / (avg_ms * 1e-3) / 1e12
         out["sieve"] = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_INT_OPS / 1e12, "unit": "Tops/s",
                         "frac": ach / (VALU_PEAK_INT_OPS / 1e12), "traffic": traffic.get("sieve"),
                         "avg_launch_ms": avg_ms, "integers_per_launch": ints_per_launch}
-    # Partition: HBM-bound, 16 B read + 16 B write per entry.
-    entries_per_step = n_keys_per_step
+    # Partition: HBM-bound, 16 B read + 16 B write per entry (the entries the
+    # sieve wrote: the integers that pass the member test).
     if ln["partition"]:
         avg_ms = ms["partition"] / ln["partition"]
         b = 2 * ENTRY_BYTES * entries_per_step * steps / ln["partition"]
@@ -230,7 +232,8 @@ def main():
     pairs, total, per_step, agg = run_plain(bx, N, args.steps, args.warmup)
     ms_step = total / args.steps * 1e3
     value = N / (total / args.steps)
-    dominant, roof = roofline_from(agg, N, args.steps, load_traffic() if args.log2n == 36 else {})
+    dominant, roof = roofline_from(agg, N, agg["entries"], args.steps,
+                                   load_traffic() if args.log2n == 36 else {})
     line = {
         "metric": "integers sieved+joined/s at N=2^36 (both kinds), %HBM roofline; batched vs plain",
         "value": value,
@@ -252,7 +255,22 @@ def main():
         "roofline_kernels": roof,
         "kernel_ms_per_step": {k: v / args.steps for k, v in agg["kernel_ms"].items()},
         "step_seconds": per_step,
+        "entries_per_step": agg["entries"],
     }
+    if not args.no_unpruned:
+        # The same search with every integer entered into the join (member test
+        # off): the pair list is identical, the join moves ~3.5x more entries.
+        log("same search without the member test ...")
+        bx.set_option("prune", 0)
+        try:
+            p0, total0, per0, agg0 = run_plain(bx, N, 1, 0)
+        finally:
+            bx.set_option("prune", 1)
+        if p0 != pairs:
+            raise SystemExit("pair lists differ with and without the member test")
+        line["without_member_test"] = {"integers_per_s": N / total0, "ms_per_step": total0 * 1e3,
+                                       "passes": agg0["passes"], "entries_per_step": agg0["entries"],
+                                       "kernel_ms_per_step": agg0["kernel_ms"]}
     if not args.no_batched or args.served > 0:
         if os.path.exists(args.tuning):
             bx.load_tuning(args.tuning)

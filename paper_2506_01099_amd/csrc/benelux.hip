@@ -45,7 +45,7 @@ int fail(int code, const std::string& msg) {
 constexpr int kTileSmall = 2048, kTileLarge = 4096;
 constexpr int kVerifyGrid = 2048;
 constexpr int kPartBlock = 1024;
-constexpr int kJoinBlock = 512;
+constexpr int kJoinBlock = 1024;
 constexpr int kVerifyBlock = 256;
 constexpr uint32_t kCandCap = 1u << 20;
 constexpr uint32_t kDefaultSegLen = 1u << 17;
@@ -106,6 +106,7 @@ struct bx_ctx {
   DenseTab* d_dense[2] = {nullptr, nullptr};
   DevBuf l1, l2, cnt1, cnt2, cand, out, flags, spill, queries, segpref, rad, acc;
   int force_passes = 0, timing = 1, verify = 1, force_b1 = -1, force_b2 = -1, force_group = 0;
+  int prune = 1;            // drop x that cannot be a pair member before the join
   int tile = kTileSmall;
   int graph_batch = 1;      // batched calls run as one captured HIP graph
   bool capturing = false;   // no event records while a stream capture is open
@@ -323,8 +324,9 @@ int make_plan(bx_ctx* c, uint64_t n_keys, uint64_t share, uint32_t sieve_grid, P
     const double region = static_cast<double>(share) / P / std::ldexp(1.0, static_cast<int>(b1));
     p.cap1 = round_up(static_cast<uint64_t>(std::ceil(region * 1.05)) + 256, 64);
     (void)W;
-    // Partitions of at most ~7.4k entries (one LDS join chunk holds 8192).
-    uint32_t b2 = bucket * 1.03 > 6500.0 ? ceil_log2(bucket * 1.03 / 6500.0) : 0;
+    // Partitions of at most ~7.3k entries on average, so that cap2 (10% slack)
+    // stays within one LDS join chunk (8192 entries).
+    uint32_t b2 = bucket * 1.03 > 7300.0 ? ceil_log2(bucket * 1.03 / 7300.0) : 0;
     if (c->force_b2 >= 0) b2 = static_cast<uint32_t>(c->force_b2);
     if (b2 > 12 || b1 + b2 > 32) {
       if (c->force_passes > 0) return fail(BX_ENOMEM, "forced pass count leaves partitions too large");
@@ -354,58 +356,127 @@ int make_plan(bx_ctx* c, uint64_t n_keys, uint64_t share, uint32_t sieve_grid, P
 struct Segs {
   std::vector<Query> q;
   std::vector<uint64_t> prefix;
-  uint64_t n_segs = 0, n_keys = 0;
+  uint64_t n_segs = 0;
+  uint64_t n_ints = 0;  // integers sieved
+  uint64_t n_keys = 0;  // bound on the entries they produce (all of them without the member test)
 };
 
-// Largest number of integers any of W sieve workgroups processes (segment s
-// goes to workgroup s mod W): it sizes the workgroup-private regions.
+// Upper bounds on the fraction of x kept by the member test (may_pair) in the
+// zones b/d_{k-1} < x <= b/d_k of a query [a, b): x <= b/11 are all kept, and
+// beyond b/2 only x with x and x + 1 non-squarefree remain (density 0.1068).
+// The zone densities are those of sets defined by squarefreeness and
+// residues mod 210, measured as 1, 0.557, 0.494, 0.393, 0.190 and 0.107 (at
+// most 0.001 above that in any window of 2^15 integers); the bounds add a
+// margin.  A region that still overflows is caught and its pass split.
+constexpr int kZones = 6;
+constexpr double kZoneDiv[kZones - 1] = {11.0, 7.0, 5.0, 3.0, 2.0};
+constexpr double kZoneRate[kZones] = {1.0, 0.58, 0.52, 0.42, 0.21, 0.125};
+
+// Zone k of query q covers x in [zone_lo(k), zone_lo(k + 1)).
+uint64_t zone_lo(const Query& q, int k) {
+  if (k == 0) return 0;
+  if (k == kZones) return UINT64_MAX;
+  return static_cast<uint64_t>(std::floor(static_cast<double>(q.b) / kZoneDiv[k - 1])) + 1;
+}
+
+double rate_at(const bx_ctx* c, const Query& q, uint64_t x) {
+  if (!c->prune) return 1.0;
+  int k = 0;
+  while (k + 1 < kZones && x >= zone_lo(q, k + 1)) ++k;
+  return kZoneRate[k];
+}
+
+// Bound on the number of kept x in [u, v) of query q.
+double kept_bound(const bx_ctx* c, const Query& q, uint64_t u, uint64_t v) {
+  if (v <= u) return 0.0;
+  if (!c->prune) return static_cast<double>(v - u);
+  double n = 0.0;
+  for (int k = 0; k < kZones; ++k) {
+    const uint64_t l = std::max(u, zone_lo(q, k)), h = std::min(v, zone_lo(q, k + 1));
+    if (h > l) n += kZoneRate[k] * static_cast<double>(h - l);
+  }
+  return n + 3.0;  // x <= 3
+}
+
+// Adds w to every workgroup that runs one of the segments [g, g + n) (segment
+// s runs on workgroup s mod W), through a difference array.
+void add_round_robin(std::vector<double>& diff, uint64_t g, uint64_t n, uint32_t W, double w) {
+  if (n == 0 || w == 0.0) return;
+  const double rounds = static_cast<double>(n / W);
+  const uint64_t rem = n % W, first = g % W;
+  diff[0] += rounds * w;
+  diff[W] -= rounds * w;
+  if (rem) {
+    const uint64_t end = first + rem;  // [first, end) mod W get one more
+    if (end <= W) {
+      diff[first] += w;
+      diff[end] -= w;
+    } else {
+      diff[first] += w;
+      diff[W] -= w;
+      diff[0] += w;
+      diff[end - W] -= w;
+    }
+  }
+}
+
+// The largest number of kept x that one sieve workgroup can produce (an upper
+// bound).  Segments run round-robin; a segment is charged at the rate of the
+// zone holding its first integer, the highest rate it touches.
 uint64_t max_share(const bx_ctx* c, const Segs& s, uint32_t W) {
   if (W == 0) return 0;
-  std::vector<int64_t> diff(W + 1, 0);  // full segments per workgroup, as a difference array
-  std::vector<uint64_t> extra(W, 0);    // the shorter last segment of each query
+  std::vector<double> diff(W + 1, 0.0);
+  std::vector<double> extra(W, 0.0);  // the shorter last segment of each query
+  const uint64_t L = c->seg_len;
   for (size_t i = 0; i < s.q.size(); ++i) {
-    const uint64_t L = s.q[i].b > s.q[i].a ? s.q[i].b - s.q[i].a : 0;
-    if (L == 0) continue;
-    const uint64_t nseg = (L + c->seg_len - 1) / c->seg_len, nfull = nseg - 1;
-    const uint64_t first = s.prefix[i] % W;
-    const uint64_t rounds = nfull / W, rem = nfull % W;
-    diff[0] += static_cast<int64_t>(rounds);
-    diff[W] -= static_cast<int64_t>(rounds);
-    if (rem) {
-      const uint64_t end = first + rem;  // [first, end) mod W get one more
-      if (end <= W) {
-        diff[first] += 1;
-        diff[end] -= 1;
-      } else {
-        diff[first] += 1;
-        diff[W] -= 1;
-        diff[0] += 1;
-        diff[end - W] -= 1;
-      }
+    const Query& q = s.q[i];
+    const uint64_t len = q.b > q.a ? q.b - q.a : 0;
+    if (len == 0) continue;
+    const uint64_t nseg = (len + L - 1) / L, nfull = nseg - 1;
+    // Full segments, split where the zone changes.
+    uint64_t k = 0;
+    while (k < nfull) {
+      const uint64_t x = q.a + k * L;
+      const double r = rate_at(c, q, x);
+      uint64_t k_end = nfull;
+      if (c->prune)
+        for (int z = 1; z < kZones; ++z) {
+          const uint64_t zl = zone_lo(q, z);
+          if (zl > x) {  // first segment whose start lies at or past zl
+            k_end = std::min(nfull, (zl - q.a + L - 1) / L);
+            break;
+          }
+        }
+      if (k_end <= k) k_end = k + 1;
+      add_round_robin(diff, s.prefix[i] + k, k_end - k, W, r * static_cast<double>(L));
+      k = k_end;
     }
-    extra[(s.prefix[i] + nfull) % W] += L - nfull * c->seg_len;
+    const uint64_t x_last = q.a + nfull * L;
+    extra[(s.prefix[i] + nfull) % W] += rate_at(c, q, x_last) * static_cast<double>(len - nfull * L) + 3.0;
   }
-  uint64_t best = 0;
-  int64_t run = 0;
+  double best = 0.0, run = 0.0;
   for (uint32_t w = 0; w < W; ++w) {
     run += diff[w];
-    best = std::max<uint64_t>(best, static_cast<uint64_t>(run) * c->seg_len + extra[w]);
+    best = std::max(best, run + extra[w]);
   }
-  return best;
+  return static_cast<uint64_t>(std::ceil(best));
 }
 
 void make_segs(const bx_ctx* c, Segs* s) {
   s->prefix.assign(s->q.size() + 1, 0);
-  uint64_t acc = 0, keys = 0;
+  s->n_ints = 0;
+  uint64_t acc = 0;
+  double keys = 0.0;
   for (size_t i = 0; i < s->q.size(); ++i) {
     s->prefix[i] = acc;
     const uint64_t L = s->q[i].b > s->q[i].a ? s->q[i].b - s->q[i].a : 0;
     acc += (L + c->seg_len - 1) / c->seg_len;
-    keys += L;
+    keys += kept_bound(c, s->q[i], s->q[i].a, s->q[i].b);
+    s->n_ints += L;
   }
   s->prefix[s->q.size()] = acc;
   s->n_segs = acc;
-  s->n_keys = keys;
+  s->n_keys = static_cast<uint64_t>(std::ceil(keys));
 }
 
 int upload_segs(bx_ctx* c, const Segs& s, hipStream_t st) {
@@ -484,7 +555,10 @@ int prepare_job(bx_ctx* c, Segs& s, int batch, uint32_t kinds, hipStream_t st, J
   j->n_regions = static_cast<uint64_t>(j->B1) * j->sieve_grid;
   j->cpr = static_cast<uint32_t>((plan.cap1 + kPartChunk - 1) / kPartChunk);
   const uint64_t chunks = static_cast<uint64_t>(j->sieve_grid) * j->cpr;  // per bucket
-  j->part_grid = 8ull * ((chunks + (8 / j->G) - 1) / (8 / j->G));
+  // Persistent partition grid: one workgroup per CU (LDS bound), a multiple
+  // of 8 so that every XCD serves its share of the group's buckets.
+  const uint64_t per = 8 / j->G;
+  j->part_grid = 8ull * std::min<uint64_t>(std::max(1, c->n_cu / 8), (chunks + per - 1) / per);
   if (j->part_grid > 0x7FFFFFFFull) return fail(BX_EINTERNAL, "partition grid too large");
   j->gmask = batch ? kGrpMask : 0u;
   j->kmask1 = kM42 | (static_cast<uint64_t>(j->gmask) << kGrpShift);
@@ -522,6 +596,7 @@ int enqueue_pass(bx_ctx* c, const Job& j, uint64_t ph_lo, uint64_t ph_hi, hipStr
   uint32_t* d_flags = static_cast<uint32_t*>(c->flags.p);
   SieveParams P = base_sieve_params(c, *j.s);
   P.batch = j.batch;
+  P.prune = c->prune;
   P.pfilter = !(ph_lo == 0 && ph_hi == (1ull << 32));
   P.ph_lo = ph_lo;
   P.ph_hi = ph_hi;
@@ -747,7 +822,7 @@ int run_search(bx_ctx* c, Segs& s, int batch, uint32_t kinds, std::vector<OutPai
   if (s.n_segs == 0) return BX_OK;
   Job j;
   if ((rc = prepare_job(c, s, batch, kinds, st, &j)) != BX_OK) return rc;
-  c->stats.integers = s.n_keys;
+  c->stats.integers = s.n_ints;
   if (use_graph) {
     int redo = 0;
     if ((rc = run_passes_graph(c, j, st, result, &redo)) != BX_OK) return rc;
@@ -991,6 +1066,8 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
     c->tile = v == 0 ? kTileSmall : static_cast<int>(v);
   } else if (n == "graph") {
     c->graph_batch = v != 0;
+  } else if (n == "prune") {
+    c->prune = v != 0;
   } else if (n == "group") {
     if (v != 0 && v != 1 && v != 2 && v != 4 && v != 8) return fail(BX_EINVAL, "group must be 0, 1, 2, 4 or 8");
     c->force_group = static_cast<int>(v);

@@ -48,6 +48,7 @@ struct SieveParams {
   uint64_t rad_lo, rad_hi;
   // MODE_KEYS
   int batch;
+  uint32_t prune;         // drop x that cannot be a member of any pair (may_pair)
   uint32_t pfilter;       // keep x only when pass_hash(key) is in [ph_lo, ph_hi)
   uint64_t ph_lo, ph_hi;
   uint32_t b1shift, b1mask;
@@ -90,10 +91,10 @@ struct SieveShSel<T, BLOCK, MODE_KEYS> {
 // bucket b: shared by all workgroups (global, one atomic per non-empty bucket)
 // or, with PRIVATE, owned by this workgroup (no atomics).  dst(b, k) stores the
 // k-th entry of the bucket (k < cap).
-template <int BLOCK, int NB, bool PRIVATE, typename Dst>
+template <int BLOCK, int NB, bool PRIVATE, typename Dst, typename Mid>
 __device__ void scatter_runs(uint32_t n, uint32_t nb, const Entry* ent, const uint16_t* sb, uint16_t* perm,
                              uint32_t* cnt, uint32_t* gofs, uint32_t* wsum, uint32_t* gcur, uint64_t cap,
-                             uint32_t* flag, Dst dst) {
+                             uint32_t* flag, Dst dst, Mid mid) {
   constexpr int BINS = (NB + BLOCK - 1) / BLOCK;
   const int tid = threadIdx.x;
   for (uint32_t b = tid; b < nb; b += BLOCK) cnt[b] = 0;
@@ -127,6 +128,7 @@ __device__ void scatter_runs(uint32_t n, uint32_t nb, const Entry* ent, const ui
     ex += loc[k];
   }
   __syncthreads();
+  mid();  // the global cursors are taken: work that may overlap the scatter
   for (uint32_t i = tid; i < n; i += BLOCK) perm[atomicAdd(&cnt[sb[i]], 1u)] = static_cast<uint16_t>(i);
   __syncthreads();
   for (uint32_t j = tid; j < n; j += BLOCK) {
@@ -149,7 +151,8 @@ __device__ void flush_stage(SieveShKeys<T, BLOCK>& sh, const SieveParams& P) {
   Entry* l1 = P.l1 + static_cast<uint64_t>(blockIdx.x) * cap1;
   scatter_runs<BLOCK, kB1Max, true>(n, P.b1mask + 1, sh.stage, sh.sb, sh.perm, sh.cnt, sh.gofs, sh.wsum, sh.lcur, cap1,
                                     &P.flags[kFlagL1Overflow],
-                                    [=](uint32_t b, uint32_t k, const Entry& e) { l1[b * W * cap1 + k] = e; });
+                                    [=](uint32_t b, uint32_t k, const Entry& e) { l1[b * W * cap1 + k] = e; },
+                                    [] {});
   if (threadIdx.x == 0) sh.stage_n = 0;
   __syncthreads();
 }
@@ -284,7 +287,7 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
         }
       } else {
         const uint32_t grp = P.batch ? qi : 0u;
-        // 1. The pass test for this thread's ITER integers (cheap, every x).
+        // 1. The member and pass tests for this thread's ITER integers (cheap, every x).
         bool keep[ITER];
         uint64_t mask[ITER];
         uint32_t total = 0;
@@ -293,13 +296,13 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
           const uint32_t i = it * BLOCK + tid;
           keep[it] = false;
           if (i < cnt) {
-            if (P.pfilter) {
-              const uint64_t a = sh.tile[i], b = sh.tile[i + 1];
-              const uint64_t ph = pass_hash(a < b ? a : b, a < b ? b : a, grp);
-              keep[it] = ph >= P.ph_lo && ph < P.ph_hi;
-            } else {
-              keep[it] = true;
+            const uint64_t r0 = sh.tile[i], r1 = sh.tile[i + 1];
+            bool k = !P.prune || may_pair(x0 + i, r0, r1, qb);
+            if (k && P.pfilter) {
+              const uint64_t ph = pass_hash(r0 < r1 ? r0 : r1, r0 < r1 ? r1 : r0, grp);
+              k = ph >= P.ph_lo && ph < P.ph_hi;
             }
+            keep[it] = k;
           }
           mask[it] = __ballot(keep[it]);
           total += __popcll(mask[it]);
@@ -375,11 +378,16 @@ struct PartParams {
 };
 
 // Second scatter of one group of first-level buckets into the group buffer.
-// Workgroup l runs on XCD l mod 8 (round-robin dispatch); with G = 8 every
-// chunk of a bucket stays on one XCD, so the partial lines of its sub-buckets
-// are completed in that XCD's L2 before they are written back.
+// Persistent: workgroup l runs on XCD l mod 8 (round-robin dispatch) and
+// serves bucket (l mod 8) mod G, so with G = 8 a bucket never leaves its XCD
+// and the partial lines of its sub-buckets are completed in that XCD's L2
+// before they are written back.  The bucket's chunks are split into nbw
+// contiguous ranges, one per workgroup; the next chunk is loaded into
+// registers while the current one is scattered.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
+  constexpr int EPT = kPartChunk / BLOCK;
+  static_assert(kPartChunk % BLOCK == 0, "chunk shape");
   __shared__ Entry ent[kPartChunk];
   __shared__ uint16_t sb[kPartChunk], perm[kPartChunk];
   __shared__ uint32_t cnt[kB2Max], gofs[kB2Max];
@@ -389,29 +397,61 @@ __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
   const uint32_t xcd = l & 7u, slot = l >> 3;
   const uint32_t per = 8u / P.G;
   const uint32_t gb = xcd % P.G;
-  const uint32_t chunk = slot * per + xcd / P.G;
+  const uint32_t k = slot * per + xcd / P.G;  // index among the bucket's nbw workgroups
+  const uint32_t nbw = (gridDim.x >> 3) * per;
   const uint32_t b1 = P.first + gb;
-  const uint32_t w = chunk / P.chunks_per_region, j = chunk % P.chunks_per_region;
-  if (w >= P.W) return;
-  const uint64_t region = static_cast<uint64_t>(b1) * P.W + w;
-  const uint64_t n1 = min(static_cast<uint64_t>(P.cnt1[region]), P.cap1);
-  const uint64_t s0 = static_cast<uint64_t>(j) * kPartChunk;
-  if (s0 >= n1) return;
-  const uint32_t n = static_cast<uint32_t>(min(static_cast<uint64_t>(kPartChunk), n1 - s0));
-  const Entry* src = P.l1 + region * P.cap1 + s0;
-  for (uint32_t i = tid; i < n; i += BLOCK) {
-    const Entry e = src[i];
-    ent[i] = e;
-    const uint32_t h = key_hash(entry_lo(e), entry_hi(e), entry_grp(e, P.gmask));
-    sb[i] = static_cast<uint16_t>((h >> P.b2shift) & P.b2mask);
-  }
-  __syncthreads();
   const uint32_t B2 = P.b2mask + 1;
+  const uint32_t cpr = P.chunks_per_region;
+  const uint64_t n_chunks = static_cast<uint64_t>(P.W) * cpr;
+  const uint64_t c_begin = n_chunks * k / nbw, c_end = n_chunks * (k + 1) / nbw;
   Entry* out = P.l2 + static_cast<uint64_t>(gb) * B2 * P.cap2;
+  uint32_t* gcur = P.cnt2 + static_cast<uint64_t>(gb) * B2;
   const uint32_t cap2 = P.cap2;
-  scatter_runs<BLOCK, kB2Max, false>(n, B2, ent, sb, perm, cnt, gofs, wsum, P.cnt2 + static_cast<uint64_t>(gb) * B2, cap2,
-                              &P.flags[kFlagL2Overflow],
-                              [=](uint32_t b, uint32_t k, const Entry& e) { out[static_cast<uint64_t>(b) * cap2 + k] = e; });
+  // Chunk ci of the bucket: entries [s0, s0 + n) of region ci / cpr.
+  auto chunk = [&](uint64_t ci, const Entry** src) -> uint32_t {
+    const uint64_t region = static_cast<uint64_t>(b1) * P.W + ci / cpr;
+    const uint64_t n1 = min(static_cast<uint64_t>(P.cnt1[region]), P.cap1);
+    const uint64_t s0 = (ci % cpr) * static_cast<uint64_t>(kPartChunk);
+    *src = P.l1 + region * P.cap1 + s0;
+    return s0 >= n1 ? 0u : static_cast<uint32_t>(min(static_cast<uint64_t>(kPartChunk), n1 - s0));
+  };
+  Entry e[EPT];
+  const Entry* src;
+  uint32_t n = c_begin < c_end ? chunk(c_begin, &src) : 0u;
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const uint32_t i = tid + q * BLOCK;
+    if (i < n) e[q] = src[i];
+  }
+  for (uint64_t ci = c_begin; ci < c_end; ++ci) {
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const uint32_t i = tid + q * BLOCK;
+      if (i < n) {
+        ent[i] = e[q];
+        const uint32_t h = key_hash(entry_lo(e[q]), entry_hi(e[q]), entry_grp(e[q], P.gmask));
+        sb[i] = static_cast<uint16_t>((h >> P.b2shift) & P.b2mask);
+      }
+    }
+    const uint32_t n_cur = n;
+    n = ci + 1 < c_end ? chunk(ci + 1, &src) : 0u;
+    // Issued after the global cursor atomics, whose returns would otherwise
+    // wait for these loads as well.
+    auto prefetch = [&] {
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const uint32_t i = tid + q * BLOCK;
+        if (i < n) e[q] = src[i];
+      }
+    };
+    __syncthreads();
+    if (n_cur)  // uniform over the workgroup
+      scatter_runs<BLOCK, kB2Max, false>(
+          n_cur, B2, ent, sb, perm, cnt, gofs, wsum, gcur, cap2, &P.flags[kFlagL2Overflow],
+          [=](uint32_t b, uint32_t kk, const Entry& x) { out[static_cast<uint64_t>(b) * cap2 + kk] = x; }, prefetch);
+    else
+      prefetch();
+  }
 }
 
 struct JoinParams {
@@ -447,7 +487,7 @@ __device__ __forceinline__ void emit_cand(const JoinParams& P, const Entry& a, c
 // joined chunk by chunk: after chunk c is inserted, every later entry probes
 // it, walking to an empty slot as the probe step does.
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_join(JoinParams P) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void k_join(JoinParams P) {
   constexpr int EPT = kJoinCap / BLOCK;
   constexpr uint32_t kEmpty = 0xFFFFFFFFu;
   constexpr uint32_t kIdxMask = (1u << kJoinIdxBits) - 1;

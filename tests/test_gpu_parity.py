@@ -42,6 +42,23 @@ def squarefree_count(n):
     return int(sum(int(mu[d]) * (n // (d * d)) for d in range(1, r + 1)))
 
 
+def member_count(N):
+    """#{1 <= x <= N : x may be a member of a pair with n <= N}, by the rule of
+    tests/test_member_test.py, vectorised over the oracle's radicals."""
+    r = oracle.radicals(1, N + 2).astype(np.int64)
+    x = np.arange(1, N + 1, dtype=np.int64)
+
+    def spf_floor(y):
+        out = np.full(y.shape, 11, dtype=np.int64)
+        for p in (7, 5, 3, 2):
+            out = np.where(y % p == 0, p, out)
+        return out
+
+    b = N + 1
+    drop = ((r[:N] == x) & (x * spf_floor(x) > b)) | ((r[1:N + 1] == x + 1) & ((x + 1) * spf_floor(x + 1) > b))
+    return int(np.count_nonzero(~drop | (x <= 3)))
+
+
 # --- radicals -----------------------------------------------------------------------
 
 @pytest.mark.parametrize("lo,hi", [
@@ -130,7 +147,26 @@ def test_search_2_24_matches_oracle(ctx):
     got = ctx.search(N)
     assert got == oracle.search(N)
     st = ctx.stats()
+    assert st["integers"] == N
+    assert st["entries"] == member_count(N)
+
+
+def test_member_test_off_same_pairs(ctx):
+    """Without the member test every x becomes an entry; the pairs are the same."""
+    N = 1 << 22
+    ctx.set_option("prune", 0)
+    try:
+        got = ctx.search(N)
+        st = ctx.stats()
+        batch = ctx.search_batch(np.array([1, 1000, 30, 4000000], dtype=np.uint64),
+                                 np.array([N + 1, 5000, 1300, N + 1], dtype=np.uint64))
+    finally:
+        ctx.set_option("prune", 1)
+    assert got == oracle.search(N)
     assert st["entries"] == N and st["integers"] == N
+    assert batch == ctx.search_batch(np.array([1, 1000, 30, 4000000], dtype=np.uint64),
+                                     np.array([N + 1, 5000, 1300, N + 1], dtype=np.uint64))
+    assert batch[0] == oracle.search(N) and batch[2] == oracle.search_range(30, 1300)
 
 
 @pytest.mark.parametrize("a,b", [(1, 9), (2, 9), (3, 9), (35, 4375), (36, 4375), (35, 4374), (126, 16129),
@@ -153,7 +189,7 @@ def test_pass_count_invariance(ctx, passes):
     finally:
         ctx.set_option("passes", 0)
     assert got == oracle.search(1 << 20)
-    assert st["passes"] >= passes and st["entries"] == 1 << 20
+    assert st["passes"] >= passes and st["entries"] == member_count(1 << 20)
 
 
 @pytest.mark.parametrize("b1,b2", [(1, 1), (2, 3), (10, 1), (3, 12), (0, 0)])
@@ -219,7 +255,8 @@ def test_search_2_32_theorem1(ctx):
     st = ctx.stats()
     assert got == theorem1_pairs(1 << 32)
     assert len(got) == 33
-    assert st["entries"] == 1 << 32
+    assert st["integers"] == 1 << 32 and 0.25 * (1 << 32) < st["entries"] < 0.30 * (1 << 32)
+    assert st["retries"] == 0
 
 
 def test_search_2_36_theorem1(ctx):
@@ -228,7 +265,8 @@ def test_search_2_36_theorem1(ctx):
     st = ctx.stats()
     assert got == theorem1_pairs(1 << 36)
     assert len(got) == 37
-    assert st["entries"] == 1 << 36 and st["passes"] >= 2
+    assert st["integers"] == 1 << 36 and 0.25 * (1 << 36) < st["entries"] < 0.30 * (1 << 36)
+    assert st["passes"] >= 2 and st["retries"] == 0
 
 
 # --- batched --------------------------------------------------------------------------
