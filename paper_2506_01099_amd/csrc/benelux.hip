@@ -361,22 +361,31 @@ struct Segs {
   uint64_t n_keys = 0;  // bound on the entries they produce (all of them without the member test)
 };
 
-// Upper bounds on the fraction of x kept by the member test (may_pair) in the
-// zones b/d_{k-1} < x <= b/d_k of a query [a, b): x <= b/11 are all kept, and
-// beyond b/2 only x with x and x + 1 non-squarefree remain (density 0.1068).
-// The zone densities are those of sets defined by squarefreeness and
-// residues mod 210, measured as 1, 0.557, 0.494, 0.393, 0.190 and 0.107 (at
-// most 0.001 above that in any window of 2^15 integers); the bounds add a
-// margin.  A region that still overflows is caught and its pass split.
-constexpr int kZones = 6;
-constexpr double kZoneDiv[kZones - 1] = {11.0, 7.0, 5.0, 3.0, 2.0};
-constexpr double kZoneRate[kZones] = {1.0, 0.58, 0.52, 0.42, 0.21, 0.125};
+// Bounds on the entries the member test (may_pair) keeps in a query [a, b):
+//  - x with x and x + 1 non-squarefree: density 0.1068, at most 0.122 in any
+//    window of 2^10 integers (0.1077 in windows of 2^15); charged at 0.125;
+//  - the other kept x lie at or below b / 2: all x <= 2 sqrt(b) may pass
+//    (charged at 1), and above that only x + 1 or x with a small radical
+//    pass: 1.1-1.2 sqrt(b) of them for b from 2^20 to 2^26, charged as
+//    2 sqrt(b) per query.
+// A region that still overflows is caught and its pass split, so these
+// bounds affect speed only.
+constexpr int kZones = 2;
+constexpr double kZoneRate[kZones] = {1.0, 0.125};
+
+double sqrt_b(const Query& q) { return std::sqrt(static_cast<double>(q.b)); }
 
 // Zone k of query q covers x in [zone_lo(k), zone_lo(k + 1)).
 uint64_t zone_lo(const Query& q, int k) {
   if (k == 0) return 0;
   if (k == kZones) return UINT64_MAX;
-  return static_cast<uint64_t>(std::floor(static_cast<double>(q.b) / kZoneDiv[k - 1])) + 1;
+  return static_cast<uint64_t>(2.0 * sqrt_b(q)) + 4;
+}
+
+// The scattered kept x above 2 sqrt(b) (none when the query lies above b / 2).
+double scattered(const bx_ctx* c, const Query& q) {
+  if (!c->prune || q.a > q.b / 2) return 0.0;
+  return 2.0 * sqrt_b(q);
 }
 
 double rate_at(const bx_ctx* c, const Query& q, uint64_t x) {
@@ -395,7 +404,7 @@ double kept_bound(const bx_ctx* c, const Query& q, uint64_t u, uint64_t v) {
     const uint64_t l = std::max(u, zone_lo(q, k)), h = std::min(v, zone_lo(q, k + 1));
     if (h > l) n += kZoneRate[k] * static_cast<double>(h - l);
   }
-  return n + 3.0;  // x <= 3
+  return n + scattered(c, q) + 3.0;  // x <= 3
 }
 
 // Adds w to every workgroup that runs one of the segments [g, g + n) (segment
@@ -454,12 +463,22 @@ uint64_t max_share(const bx_ctx* c, const Segs& s, uint32_t W) {
     const uint64_t x_last = q.a + nfull * L;
     extra[(s.prefix[i] + nfull) % W] += rate_at(c, q, x_last) * static_cast<double>(len - nfull * L) + 3.0;
   }
+  // The scattered kept x of each query, charged to every workgroup at four
+  // times an even spread over the query's segments.
+  double spread = 0.0;
+  for (size_t i = 0; i < s.q.size(); ++i) {
+    const double sc = scattered(c, s.q[i]);
+    if (sc == 0.0) continue;
+    const uint64_t nseg = s.prefix[i + 1] - s.prefix[i];
+    const double per = 4.0 * sc * static_cast<double>((nseg + W - 1) / W) / static_cast<double>(std::max<uint64_t>(1, nseg));
+    spread += std::min(sc, per) + 64.0;
+  }
   double best = 0.0, run = 0.0;
   for (uint32_t w = 0; w < W; ++w) {
     run += diff[w];
     best = std::max(best, run + extra[w]);
   }
-  return static_cast<uint64_t>(std::ceil(best));
+  return static_cast<uint64_t>(std::ceil(best + spread));
 }
 
 void make_segs(const bx_ctx* c, Segs* s) {

@@ -122,32 +122,25 @@ __device__ __forceinline__ uint64_t strip_two(uint64_t x) {
   return tz >= 2 ? (x >> (tz - 1)) : x;
 }
 
-// A lower bound on the smallest prime factor of y > 1: the first of 2, 3, 5
-// and 7 that divides y, else 11.  y < 2^43 is reduced mod 105 = 3 * 5 * 7
-// through its 32-bit halves (2^32 = 46 mod 105).
-__device__ __forceinline__ uint32_t spf_floor(uint64_t y) {
-  if ((y & 1) == 0) return 2;
-  const uint32_t lo = static_cast<uint32_t>(y), hi = static_cast<uint32_t>(y >> 32);
-  const uint32_t r = (lo % 105u + hi * 46u) % 105u;
-  if (r % 3u == 0) return 3;
-  if (r % 5u == 0) return 5;
-  if (r % 7u == 0) return 7;
-  return 11;
+// u * v <= b for u, v, b < 2^43, without overflow.
+__device__ __forceinline__ bool prod_le(uint64_t u, uint64_t v, uint64_t b) {
+  return __umul64hi(u, v) == 0 && u * v <= b;
 }
 
 // Whether x can be a member of a pair (m, n) with m < n < b, given
 // r0 = rad(x) and r1 = rad(x + 1).  Both kinds:
-//  - the larger member n has n and n + 1 non-squarefree, except n = 3 in (2, 3):
-//    a squarefree n or n + 1 would be the radical of a smaller number;
-//  - if the smaller member m is squarefree, n or n + 1 is a multiple m * t
-//    with t >= 2 whose primes divide m, so m * spf(m) <= b; the same holds
-//    for m + 1, except n = m + 1, which forces (m, n) = (2, 3).
-// So x with x or x + 1 squarefree is kept only under those bounds (x <= 3 is
-// always kept); x with both non-squarefree is always kept.
+//  - the larger member n has n and n + 1 non-squarefree, except n = 3 in
+//    (2, 3): a squarefree n or n + 1 would be the radical of a smaller number;
+//  - if the smaller member m is squarefree, n or n + 1 equals m * t with
+//    t >= 2, and every prime of m + 1 divides t - 1 (first kind) or t + 1
+//    (second kind), so t >= max(2, rad(m + 1) - 1) and m * t <= b; the same
+//    holds for m + 1 with rad(m), except t = 1, which forces (m, n) = (2, 3).
+// So x is kept if x <= 3, or if every squarefree y of {x, x + 1} passes
+// y * max(2, rad(other) - 1) <= b; x with both non-squarefree always passes.
 __device__ __forceinline__ bool may_pair(uint64_t x, uint64_t r0, uint64_t r1, uint64_t b) {
   if (x <= 3) return true;
-  if (r0 == x && x * spf_floor(x) > b) return false;
-  if (r1 == x + 1 && (x + 1) * spf_floor(x + 1) > b) return false;
+  if (r0 == x && !prod_le(x, r1 >= 3 ? r1 - 1 : 2, b)) return false;
+  if (r1 == x + 1 && !prod_le(x + 1, r0 >= 3 ? r0 - 1 : 2, b)) return false;
   return true;
 }
 

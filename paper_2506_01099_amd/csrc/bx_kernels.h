@@ -287,6 +287,9 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
         }
       } else {
         const uint32_t grp = P.batch ? qi : 0u;
+        // Above b/2 no squarefree x or x + 1 passes the member test (the
+        // factor t is at least 2): only both-non-squarefree x remain.
+        const bool upper = x0 > 3 && x0 > (qb >> 1);
         // 1. The member and pass tests for this thread's ITER integers (cheap, every x).
         bool keep[ITER];
         uint64_t mask[ITER];
@@ -297,7 +300,8 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
           keep[it] = false;
           if (i < cnt) {
             const uint64_t r0 = sh.tile[i], r1 = sh.tile[i + 1];
-            bool k = !P.prune || may_pair(x0 + i, r0, r1, qb);
+            bool k = true;
+            if (P.prune) k = upper ? (r0 != x0 + i && r1 != x0 + i + 1) : may_pair(x0 + i, r0, r1, qb);
             if (k && P.pfilter) {
               const uint64_t ph = pass_hash(r0 < r1 ? r0 : r1, r0 < r1 ? r1 : r0, grp);
               k = ph >= P.ph_lo && ph < P.ph_hi;

@@ -44,19 +44,16 @@ def squarefree_count(n):
 
 def member_count(N):
     """#{1 <= x <= N : x may be a member of a pair with n <= N}, by the rule of
-    tests/test_member_test.py, vectorised over the oracle's radicals."""
+    tests/test_member_test.py, vectorised over the oracle's radicals (exact in
+    int64 for N <= 2^30)."""
+    assert N <= 1 << 30
     r = oracle.radicals(1, N + 2).astype(np.int64)
     x = np.arange(1, N + 1, dtype=np.int64)
-
-    def spf_floor(y):
-        out = np.full(y.shape, 11, dtype=np.int64)
-        for p in (7, 5, 3, 2):
-            out = np.where(y % p == 0, p, out)
-        return out
-
+    r0, r1 = r[:N], r[1:N + 1]
     b = N + 1
-    drop = ((r[:N] == x) & (x * spf_floor(x) > b)) | ((r[1:N + 1] == x + 1) & ((x + 1) * spf_floor(x + 1) > b))
-    return int(np.count_nonzero(~drop | (x <= 3)))
+    drop0 = (r0 == x) & (x * np.maximum(2, r1 - 1) > b)
+    drop1 = (r1 == x + 1) & ((x + 1) * np.maximum(2, r0 - 1) > b)
+    return int(np.count_nonzero((x <= 3) | ~(drop0 | drop1)))
 
 
 # --- radicals -----------------------------------------------------------------------
@@ -255,7 +252,7 @@ def test_search_2_32_theorem1(ctx):
     st = ctx.stats()
     assert got == theorem1_pairs(1 << 32)
     assert len(got) == 33
-    assert st["integers"] == 1 << 32 and 0.25 * (1 << 32) < st["entries"] < 0.30 * (1 << 32)
+    assert st["integers"] == 1 << 32 and 0.106 * (1 << 32) < st["entries"] < 0.108 * (1 << 32)
     assert st["retries"] == 0
 
 
@@ -265,8 +262,8 @@ def test_search_2_36_theorem1(ctx):
     st = ctx.stats()
     assert got == theorem1_pairs(1 << 36)
     assert len(got) == 37
-    assert st["integers"] == 1 << 36 and 0.25 * (1 << 36) < st["entries"] < 0.30 * (1 << 36)
-    assert st["passes"] >= 2 and st["retries"] == 0
+    assert st["integers"] == 1 << 36 and 0.106 * (1 << 36) < st["entries"] < 0.108 * (1 << 36)
+    assert st["retries"] == 0
 
 
 # --- batched --------------------------------------------------------------------------
