@@ -158,8 +158,13 @@ int bx_get_stats(bx_ctx* ctx, bx_stats* out);
  *   "b1_bits"      force the first partition fan-out (0 = plan)
  *   "b2_bits"      force the second partition fan-out (0 = plan)
  *   "group"        first-level buckets per second-level launch (1, 2, 4, 8; 0 = 8)
- *   "tile"         sieve LDS tile: 2048 (two workgroups per CU) or 4096 (0 = 2048)
- *   "graph"        1 = batched calls run as one captured HIP graph (default 1)  */
+ *   "tile"         sieve LDS tile: 2048 (two workgroups per CU) or 4096 (one; 0 = 4096)
+ *   "graph"        1 = batched calls run as one captured HIP graph (default 1)
+ *   "prune"        1 = only integers that can be a member of a pair enter the
+ *                  join (default 1; the pair lists are the same either way:
+ *                  a pair's larger member n has n and n+1 non-squarefree, and
+ *                  a squarefree smaller member m has n or n+1 = m*t with
+ *                  t >= max(2, rad(m+1) - 1), likewise for m+1)  */
 int bx_set_option(bx_ctx* ctx, const char* name, int64_t value);
 
 void bx_free(void* p);

@@ -43,6 +43,7 @@ int fail(int code, const std::string& msg) {
 // Two sieve shapes: LDS tiles of 2048 values with 512 threads (under 80 KB of
 // LDS, two workgroups per CU) or 4096 values with 1024 threads (one per CU).
 constexpr int kTileSmall = 2048, kTileLarge = 4096;
+constexpr int kTileDefault = kTileLarge;  // one 1024-thread workgroup per CU
 constexpr int kVerifyGrid = 2048;
 constexpr int kPartBlock = 1024;
 constexpr int kJoinBlock = 1024;
@@ -107,7 +108,7 @@ struct bx_ctx {
   DevBuf l1, l2, cnt1, cnt2, cand, out, flags, spill, queries, segpref, rad, acc;
   int force_passes = 0, timing = 1, verify = 1, force_b1 = -1, force_b2 = -1, force_group = 0;
   int prune = 1;            // drop x that cannot be a pair member before the join
-  int tile = kTileSmall;
+  int tile = kTileDefault;
   int graph_batch = 1;      // batched calls run as one captured HIP graph
   bool capturing = false;   // no event records while a stream capture is open
   hipGraphExec_t graph_exec = nullptr;
@@ -305,8 +306,8 @@ uint64_t fixed_bytes(const bx_ctx* c, uint32_t sieve_grid) {
 // fan-outs.  One pass's entries live in the first-level buckets (16 B each);
 // the second level only needs a buffer for one group of buckets at a time, so
 // the budget sets P through the first level alone.  Second-level partitions
-// end up near 1600-2400 entries, which one workgroup joins in LDS.
-int make_plan(bx_ctx* c, uint64_t n_keys, uint64_t share, uint32_t sieve_grid, Plan* out) {
+// end up near 3800-7600 entries, which one workgroup joins in LDS.
+int make_plan(bx_ctx* c, uint64_t n_keys, uint64_t n_expect, uint64_t share, uint32_t sieve_grid, Plan* out) {
   const uint64_t fixed = fixed_bytes(c, sieve_grid);
   const uint32_t p_first = c->force_passes > 0 ? static_cast<uint32_t>(c->force_passes) : 1;
   const uint32_t p_last = c->force_passes > 0 ? p_first : 4096;
@@ -314,7 +315,8 @@ int make_plan(bx_ctx* c, uint64_t n_keys, uint64_t share, uint32_t sieve_grid, P
   for (uint32_t P = p_first; P <= p_last; ++P) {
     Plan p;
     p.passes = P;
-    const double n_pass = std::max(1.0, std::ceil(static_cast<double>(n_keys) / P));
+    // Fan-outs from the expected entries per pass; the regions from the bound.
+    const double n_pass = std::max(1.0, std::ceil(static_cast<double>(std::min(n_expect, n_keys)) / P));
     uint32_t b1 = n_pass > 16384.0 ? std::min<uint32_t>(10, ceil_log2(n_pass / 16384.0)) : 0;
     if (c->force_b1 >= 0) b1 = static_cast<uint32_t>(c->force_b1);
     p.b1bits = b1;
@@ -324,9 +326,10 @@ int make_plan(bx_ctx* c, uint64_t n_keys, uint64_t share, uint32_t sieve_grid, P
     const double region = static_cast<double>(share) / P / std::ldexp(1.0, static_cast<int>(b1));
     p.cap1 = round_up(static_cast<uint64_t>(std::ceil(region * 1.05)) + 256, 64);
     (void)W;
-    // Partitions of at most ~7.3k entries on average, so that cap2 (10% slack)
-    // stays within one LDS join chunk (8192 entries).
-    uint32_t b2 = bucket * 1.03 > 7300.0 ? ceil_log2(bucket * 1.03 / 7300.0) : 0;
+    // Partitions of at most ~7.6k entries on average: with the bucket-to-bucket
+    // spread (3%) and the partition-to-partition spread (a few sigma of ~90)
+    // they stay within one LDS join chunk (8192 entries).
+    uint32_t b2 = bucket * 1.03 > 7600.0 ? ceil_log2(bucket * 1.03 / 7600.0) : 0;
     if (c->force_b2 >= 0) b2 = static_cast<uint32_t>(c->force_b2);
     if (b2 > 12 || b1 + b2 > 32) {
       if (c->force_passes > 0) return fail(BX_ENOMEM, "forced pass count leaves partitions too large");
@@ -358,7 +361,8 @@ struct Segs {
   std::vector<uint64_t> prefix;
   uint64_t n_segs = 0;
   uint64_t n_ints = 0;  // integers sieved
-  uint64_t n_keys = 0;  // bound on the entries they produce (all of them without the member test)
+  uint64_t n_keys = 0;    // bound on the entries they produce (all of them without the member test)
+  uint64_t n_expect = 0;  // expected entries
 };
 
 // Bounds on the entries the member test (may_pair) keeps in a query [a, b):
@@ -393,6 +397,17 @@ double rate_at(const bx_ctx* c, const Query& q, uint64_t x) {
   int k = 0;
   while (k + 1 < kZones && x >= zone_lo(q, k + 1)) ++k;
   return kZoneRate[k];
+}
+
+// Expected number of kept x in query q: the both-non-squarefree density
+// (0.1068, at most 0.1077 in any window of 2^15), the low zone and ~1.2 sqrt(b)
+// scattered ones.
+double kept_expected(const bx_ctx* c, const Query& q) {
+  if (q.b <= q.a) return 0.0;
+  if (!c->prune) return static_cast<double>(q.b - q.a);
+  const uint64_t low = std::min(q.b, std::max(q.a, zone_lo(q, 1)));
+  return static_cast<double>(low - q.a) + 0.108 * static_cast<double>(q.b - low) +
+         (q.a > q.b / 2 ? 0.0 : 1.2 * sqrt_b(q)) + 3.0;
 }
 
 // Bound on the number of kept x in [u, v) of query q.
@@ -485,17 +500,19 @@ void make_segs(const bx_ctx* c, Segs* s) {
   s->prefix.assign(s->q.size() + 1, 0);
   s->n_ints = 0;
   uint64_t acc = 0;
-  double keys = 0.0;
+  double keys = 0.0, expect = 0.0;
   for (size_t i = 0; i < s->q.size(); ++i) {
     s->prefix[i] = acc;
     const uint64_t L = s->q[i].b > s->q[i].a ? s->q[i].b - s->q[i].a : 0;
     acc += (L + c->seg_len - 1) / c->seg_len;
     keys += kept_bound(c, s->q[i], s->q[i].a, s->q[i].b);
+    expect += kept_expected(c, s->q[i]);
     s->n_ints += L;
   }
   s->prefix[s->q.size()] = acc;
   s->n_segs = acc;
   s->n_keys = static_cast<uint64_t>(std::ceil(keys));
+  s->n_expect = static_cast<uint64_t>(std::ceil(expect));
 }
 
 int upload_segs(bx_ctx* c, const Segs& s, hipStream_t st) {
@@ -565,7 +582,8 @@ int prepare_job(bx_ctx* c, Segs& s, int batch, uint32_t kinds, hipStream_t st, J
   j->kinds = kinds;
   j->sieve_grid =
       static_cast<uint32_t>(std::min<uint64_t>(s.n_segs, static_cast<uint64_t>(c->n_cu) * sieve_wg_per_cu(c)));
-  if ((rc = make_plan(c, s.n_keys, max_share(c, s, j->sieve_grid), j->sieve_grid, &j->plan)) != BX_OK) return rc;
+  if ((rc = make_plan(c, s.n_keys, s.n_expect, max_share(c, s, j->sieve_grid), j->sieve_grid, &j->plan)) != BX_OK)
+    return rc;
   const Plan& plan = j->plan;
   j->B1 = 1u << plan.b1bits;
   j->B2 = 1u << plan.b2bits;
@@ -1082,7 +1100,7 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
     c->verify = v != 0;
   } else if (n == "tile") {
     if (v != 0 && v != kTileSmall && v != kTileLarge) return fail(BX_EINVAL, "tile must be 0, 2048 or 4096");
-    c->tile = v == 0 ? kTileSmall : static_cast<int>(v);
+    c->tile = v == 0 ? kTileDefault : static_cast<int>(v);
   } else if (n == "graph") {
     c->graph_batch = v != 0;
   } else if (n == "prune") {

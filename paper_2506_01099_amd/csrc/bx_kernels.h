@@ -26,6 +26,7 @@ constexpr int kHitCap = 1024;      // sparse-hit list held in LDS per segment
 constexpr int kB1Max = 1024;       // first partition fan-out
 constexpr int kB2Max = 4096;       // second partition fan-out
 constexpr int kPartChunk = 4096;   // entries per workgroup in k_partition
+constexpr int kStageMarginDiv = 4; // the stage is written out once less than T/4 is free
 constexpr int kJoinCap = 8192;     // entries of one LDS join chunk (held in registers)
 constexpr int kJoinSlots = 16384;  // LDS hash-table slots (load <= 0.5)
 constexpr int kJoinIdxBits = 14;   // slot = tag (18 bits) << 14 | entry index
@@ -61,8 +62,8 @@ template <int T, int BLOCK>
 struct SieveShCommon {
   uint64_t tile[T + 1];
   uint64_t hits[kHitCap];
-  uint32_t dres[kDenseMax], doff[kDenseMax], dq[kDenseMax];
-  uint32_t hit_n, n_act, stage_n, tile_kept, tile_pos, pad0, pad1, pad2;
+  uint32_t dres[kDenseMax], doff[kDenseMax], dq[kDenseMax], dtq[kDenseMax];
+  uint32_t hit_n, n_act, stage_n, pad0;
   uint32_t wsum[BLOCK / 64];
 };
 
@@ -146,7 +147,7 @@ __device__ void scatter_runs(uint32_t n, uint32_t nb, const Entry* ent, const ui
 template <int T, int BLOCK>
 __device__ void flush_stage(SieveShKeys<T, BLOCK>& sh, const SieveParams& P) {
   __syncthreads();
-  const uint32_t n = sh.stage_n;
+  const uint32_t n = min(sh.stage_n, static_cast<uint32_t>(T));  // later slots went straight out
   const uint64_t cap1 = P.cap1, W = gridDim.x;
   Entry* l1 = P.l1 + static_cast<uint64_t>(blockIdx.x) * cap1;
   scatter_runs<BLOCK, kB1Max, true>(n, P.b1mask + 1, sh.stage, sh.sb, sh.perm, sh.cnt, sh.gofs, sh.wsum, sh.lcur, cap1,
@@ -167,7 +168,10 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
   const int tid = threadIdx.x;
   const DenseTab* D = P.dense;
   const uint32_t nd = D->n, nslots = D->nslots;
-  for (uint32_t i = tid; i < nd; i += BLOCK) sh.dq[i] = D->q[i];
+  for (uint32_t i = tid; i < nd; i += BLOCK) {
+    sh.dq[i] = D->q[i];
+    sh.dtq[i] = static_cast<uint32_t>(T) % D->q[i];
+  }
   // The dense schedule is the same for every tile: each thread keeps its
   // slots (power index, multiple index, q, p, p^-1) in registers.
   uint32_t sd[SLOTS], sj[SLOTS], sq[SLOTS], sp[SLOTS], spinv[SLOTS];
@@ -191,8 +195,6 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
   }
   if (tid == 0) {
     sh.stage_n = 0;
-    sh.tile_kept = 0;
-    sh.tile_pos = 0;
   }
   if constexpr (MODE == MODE_KEYS) {
     for (uint32_t b = tid; b < kB1Max; b += BLOCK) sh.lcur[b] = 0;
@@ -252,13 +254,24 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
     const uint32_t nh = min(sh.hit_n, kHitCap + P.spill_cap);
 
     for (uint32_t base = 0; base < len; base += T) {
+      if constexpr (MODE == MODE_KEYS) {
+        // Written out once less than the margin is free; stage_n is stable
+        // here (after the previous barrier), so the decision is uniform.
+        if (sh.stage_n > static_cast<uint32_t>(T - T / kStageMarginDiv)) flush_stage<T, BLOCK>(sh, P);
+      }
       const uint32_t cnt = min(static_cast<uint32_t>(T), len - base);
       const uint64_t x0 = start + base;
       // r[n] <- n with the prime 2 already reduced (count trailing zeros).
       for (uint32_t i = tid; i <= cnt; i += BLOCK) sh.tile[i] = strip_two(x0 + i);
+      // dres[d] = x0 mod q_d, advanced by T mod q_d from tile to tile.
       if (static_cast<uint32_t>(tid) < nd) {
         const uint32_t qd = sh.dq[tid];
-        const uint32_t r = (sh.dres[tid] + base % qd) % qd;
+        uint32_t r = sh.dres[tid];
+        if (base) {
+          r += sh.dtq[tid];
+          if (r >= qd) r -= qd;
+          sh.dres[tid] = r;
+        }
         sh.doff[tid] = r ? qd - r : 0u;
       }
       __syncthreads();
@@ -269,9 +282,18 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
         const uint32_t pos = sh.doff[sd[k]] + sj[k] * sq[k];
         if (pos <= cnt) lds_div(&sh.tile[pos], sp[k], spinv[k]);
       }
-      // Sparse hits of this tile.
-      for (uint32_t h = tid; h < nh; h += BLOCK) {
-        const uint64_t e = h < kHitCap ? sh.hits[h] : spill[h - kHitCap];
+      // Sparse hits of this tile: the LDS list, then the rare spill.
+      const uint32_t nh_lds = min(nh, static_cast<uint32_t>(kHitCap));
+      for (uint32_t h = tid; h < nh_lds; h += BLOCK) {
+        const uint64_t e = sh.hits[h];
+        const uint32_t pos = static_cast<uint32_t>(e >> 32);
+        if (pos >= base && pos <= base + cnt) {
+          const uint32_t p = static_cast<uint32_t>(e);
+          lds_div(&sh.tile[pos - base], p, inv32(p));
+        }
+      }
+      for (uint32_t h = kHitCap + tid; h < nh; h += BLOCK) {
+        const uint64_t e = spill[h - kHitCap];
         const uint32_t pos = static_cast<uint32_t>(e >> 32);
         if (pos >= base && pos <= base + cnt) {
           const uint32_t p = static_cast<uint32_t>(e);
@@ -311,51 +333,48 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
           mask[it] = __ballot(keep[it]);
           total += __popcll(mask[it]);
         }
-        // 2. The tile's kept count decides whether the stage is written out
-        // first: a flush only when the tile's entries would not fit.  stage_n
-        // and tile_kept do not change between the barrier and the decision
-        // (stage_n only moves after the end-of-tile barrier), so every thread
-        // takes the same decision.
-        if (total && lane_id() == 0) atomicAdd(&sh.tile_kept, total);
-        __syncthreads();
-        if (sh.stage_n + sh.tile_kept > static_cast<uint32_t>(T)) flush_stage<T, BLOCK>(sh, P);
-        const uint32_t stage_base = sh.stage_n, kept = sh.tile_kept;
-        // 3. Compaction: ballots rank every kept lane, lane 0 reserves the
-        // wave's part of the list of kept tile positions (the flush's
-        // permutation array, free outside a flush).
-        if (total) {
+        // 2. Wave-local compaction: ballots rank the wave's kept integers in
+        // the wave's slice of the flush's permutation array (free outside a
+        // flush), and lane 0 reserves their stage slots with one LDS atomic.
+        if (total) {  // uniform over the wave
           const uint32_t lane = lane_id();
           const uint64_t below = (1ull << lane) - 1ull;
+          uint16_t* wl = sh.perm + (tid >> 6) * (ITER * 64);
           uint32_t wb = 0;
-          if (lane == 0) wb = atomicAdd(&sh.tile_pos, total);
-          wb = __builtin_amdgcn_readfirstlane(wb);
 #pragma unroll
           for (int it = 0; it < ITER; ++it) {
-            if (keep[it]) sh.perm[wb + __popcll(mask[it] & below)] = static_cast<uint16_t>(it * BLOCK + tid);
+            if (keep[it]) wl[wb + __popcll(mask[it] & below)] = static_cast<uint16_t>(it * BLOCK + tid);
             wb += __popcll(mask[it]);
           }
-        }
-        __syncthreads();
-        // 4. Entries of the kept integers only, no divergence on the pass test.
-        for (uint32_t k = tid; k < kept; k += BLOCK) {
-          const uint32_t i = sh.perm[k];
-          const uint64_t a = sh.tile[i], b = sh.tile[i + 1];
-          const uint64_t klo = a < b ? a : b, khi = a < b ? b : a;
-          const uint64_t x = x0 + i;
-          sh.stage[stage_base + k] = make_entry(klo, khi, P.batch ? x - qa : x, grp, a > b ? 1u : 0u);
-          sh.sb[stage_base + k] = static_cast<uint16_t>((key_hash(klo, khi, grp) >> P.b1shift) & P.b1mask);
+          uint32_t sbase = 0;
+          if (lane == 0) sbase = atomicAdd(&sh.stage_n, total);
+          sbase = __builtin_amdgcn_readfirstlane(sbase);
+          __builtin_amdgcn_wave_barrier();  // LDS runs one wave's accesses in order
+          // 3. Entries of the kept integers, densely over the wave's lanes.
+          // Slots past the stage (a tile that keeps more than the margin left
+          // free) go straight to the workgroup's regions.
+          for (uint32_t k = lane; k < total; k += 64) {
+            const uint32_t i = wl[k];
+            const uint64_t a = sh.tile[i], b = sh.tile[i + 1];
+            const uint64_t klo = a < b ? a : b, khi = a < b ? b : a;
+            const uint64_t x = x0 + i;
+            const Entry e = make_entry(klo, khi, P.batch ? x - qa : x, grp, a > b ? 1u : 0u);
+            const uint32_t bk = (key_hash(klo, khi, grp) >> P.b1shift) & P.b1mask;
+            const uint32_t slot = sbase + k;
+            if (slot < static_cast<uint32_t>(T)) {
+              sh.stage[slot] = e;
+              sh.sb[slot] = static_cast<uint16_t>(bk);
+            } else {
+              const uint32_t g = atomicAdd(&sh.lcur[bk], 1u);
+              if (g < P.cap1)
+                P.l1[(static_cast<uint64_t>(bk) * gridDim.x + blockIdx.x) * P.cap1 + g] = e;
+              else
+                atomicOr(&P.flags[kFlagL1Overflow], 1u);
+            }
+          }
         }
       }
       __syncthreads();
-      if constexpr (MODE == MODE_KEYS) {
-        // Every thread has read stage_n and tile_kept for this tile (before
-        // the barrier above); the next tile reads them after its own barriers.
-        if (tid == 0) {
-          sh.stage_n += sh.tile_kept;
-          sh.tile_kept = 0;
-          sh.tile_pos = 0;
-        }
-      }
     }
   }
   if constexpr (MODE == MODE_KEYS) {
