@@ -49,7 +49,7 @@ constexpr int kPartBlock = 1024;
 constexpr int kJoinBlock = 1024;
 constexpr int kVerifyBlock = 256;
 constexpr uint32_t kCandCap = 1u << 20;
-constexpr uint32_t kDefaultSegLen = 1u << 17;
+constexpr uint32_t kDefaultSegLen = 1u << 18;
 constexpr uint64_t kMaxQueryLen = 1ull << 28;
 constexpr uint32_t kMaxQueries = kGrpMask + 1;
 

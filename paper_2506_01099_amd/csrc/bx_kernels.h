@@ -22,7 +22,10 @@ namespace bx {
 constexpr int MODE_RAD = 0;
 constexpr int MODE_KEYS = 1;
 
-constexpr int kHitCap = 1024;      // sparse-hit list held in LDS per segment
+// Sparse-hit list held in LDS per segment: 1024 entries with the 2048 tile
+// (two workgroups per CU), 2048 with the 4096 tile.
+template <int T>
+constexpr int hit_cap() { return T >= 4096 ? 2048 : 1024; }
 constexpr int kB1Max = 1024;       // first partition fan-out
 constexpr int kB2Max = 4096;       // second partition fan-out
 constexpr int kPartChunk = 4096;   // entries per workgroup in k_partition
@@ -61,7 +64,7 @@ struct SieveParams {
 template <int T, int BLOCK>
 struct SieveShCommon {
   uint64_t tile[T + 1];
-  uint64_t hits[kHitCap];
+  uint64_t hits[hit_cap<T>()];
   uint32_t dres[kDenseMax], doff[kDenseMax], dq[kDenseMax], dtq[kDenseMax];
   uint32_t hit_n, n_act, stage_n, pad0;
   uint32_t wsum[BLOCK / 64];
@@ -161,6 +164,7 @@ __device__ void flush_stage(SieveShKeys<T, BLOCK>& sh, const SieveParams& P) {
 template <int T, int BLOCK, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
   using Sh = typename SieveShSel<T, BLOCK, MODE>::type;
+  constexpr uint32_t kHitCap = hit_cap<T>();
   static_assert(T % BLOCK == 0 && T <= 65536, "tile shape");
   constexpr int ITER = T / BLOCK;                                     // keys per thread per tile
   constexpr int SLOTS = (kDenseSlotMax + BLOCK - 1) / BLOCK;          // dense slots per thread
@@ -217,6 +221,16 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
     const uint64_t start = qa + (s - P.seg_prefix[qi]) * static_cast<uint64_t>(P.seg_len);
     const uint32_t len = static_cast<uint32_t>(min(static_cast<uint64_t>(P.seg_len), qb - start));
     const uint64_t V = start + len;  // largest value sieved in this segment
+    // Member test below b/2: y * M <= b fails for every y of the segment when
+    // M > lim_hi and holds for every y when M <= lim_lo (y in [start, V]);
+    // only M in between needs the exact product.  Both limits are
+    // conservative roundings of double quotients.
+    uint64_t lim_hi = 0, lim_lo = 0;
+    if (MODE == MODE_KEYS && P.prune) {
+      const double bd = static_cast<double>(qb);
+      lim_hi = static_cast<uint64_t>(bd / static_cast<double>(start > 0 ? start : 1) * (1.0 + 1e-9)) + 1;
+      lim_lo = static_cast<uint64_t>(bd / static_cast<double>(V) * (1.0 - 1e-9));
+    }
     if (tid == 0) {
       uint32_t l = P.n_dense, h = P.n_pp;
       while (l < h) {
@@ -283,7 +297,7 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
         if (pos <= cnt) lds_div(&sh.tile[pos], sp[k], spinv[k]);
       }
       // Sparse hits of this tile: the LDS list, then the rare spill.
-      const uint32_t nh_lds = min(nh, static_cast<uint32_t>(kHitCap));
+      const uint32_t nh_lds = min(nh, kHitCap);
       for (uint32_t h = tid; h < nh_lds; h += BLOCK) {
         const uint64_t e = sh.hits[h];
         const uint32_t pos = static_cast<uint32_t>(e >> 32);
@@ -312,24 +326,50 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
         // Above b/2 no squarefree x or x + 1 passes the member test (the
         // factor t is at least 2): only both-non-squarefree x remain.
         const bool upper = x0 > 3 && x0 > (qb >> 1);
-        // 1. The member and pass tests for this thread's ITER integers (cheap, every x).
+        // 1. The member and pass tests for this thread's ITER integers (cheap,
+        // every x).  The tile holds T + 1 values, so the loads need no guard;
+        // every branch below is uniform over the wave.
+        uint64_t ra[ITER], rb[ITER];
+#pragma unroll
+        for (int it = 0; it < ITER; ++it) {
+          const uint32_t i = it * BLOCK + tid;
+          ra[it] = sh.tile[i];
+          rb[it] = sh.tile[i + 1];
+        }
         bool keep[ITER];
         uint64_t mask[ITER];
         uint32_t total = 0;
 #pragma unroll
         for (int it = 0; it < ITER; ++it) {
           const uint32_t i = it * BLOCK + tid;
-          keep[it] = false;
-          if (i < cnt) {
-            const uint64_t r0 = sh.tile[i], r1 = sh.tile[i + 1];
-            bool k = true;
-            if (P.prune) k = upper ? (r0 != x0 + i && r1 != x0 + i + 1) : may_pair(x0 + i, r0, r1, qb);
-            if (k && P.pfilter) {
-              const uint64_t ph = pass_hash(r0 < r1 ? r0 : r1, r0 < r1 ? r1 : r0, grp);
-              k = ph >= P.ph_lo && ph < P.ph_hi;
+          const uint64_t r0 = ra[it], r1 = rb[it];
+          const uint64_t x = x0 + i;
+          bool k = true;
+          if (P.prune) {
+            const bool s0 = r0 == x, s1 = r1 == x + 1;  // x, x + 1 squarefree
+            k = !s0 && !s1;
+            if (!upper) {
+              // may_pair: a squarefree y of {x, x + 1} needs y * M <= b with
+              // M = max(2, rad(other) - 1).  M > lim_hi fails for the whole
+              // segment, which settles almost every such y at once; the rest
+              // (M <= lim_hi, i.e. rad(other) <= lim_hi + 1) are taken exactly.
+              const bool c0 = s0 && r1 <= lim_hi + 1, c1 = s1 && r0 <= lim_hi + 1;
+              if (__ballot(c0 || c1)) {
+                if (c0 || c1) {
+                  const uint64_t M0 = r1 >= 3 ? r1 - 1 : 2, M1 = r0 >= 3 ? r0 - 1 : 2;
+                  const bool p0 = !s0 || (c0 && (M0 <= lim_lo || prod_le(x, M0, qb)));
+                  const bool p1 = !s1 || (c1 && (M1 <= lim_lo || prod_le(x + 1, M1, qb)));
+                  k = p0 && p1;
+                }
+              }
+              if (x0 <= 3) k = k || x <= 3;
             }
-            keep[it] = k;
           }
+          if (P.pfilter) {
+            const uint64_t ph = pass_hash(r0 < r1 ? r0 : r1, r0 < r1 ? r1 : r0, grp);
+            k = k && ph >= P.ph_lo && ph < P.ph_hi;
+          }
+          keep[it] = k && i < cnt;
           mask[it] = __ballot(keep[it]);
           total += __popcll(mask[it]);
         }
