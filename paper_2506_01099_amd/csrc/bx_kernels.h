@@ -276,7 +276,10 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
       const uint32_t cnt = min(static_cast<uint32_t>(T), len - base);
       const uint64_t x0 = start + base;
       // r[n] <- n with the prime 2 already reduced (count trailing zeros).
-      for (uint32_t i = tid; i <= cnt; i += BLOCK) sh.tile[i] = strip_two(x0 + i);
+      // The whole tile is written (values past cnt are never used).
+#pragma unroll
+      for (int it = 0; it < ITER; ++it) sh.tile[it * BLOCK + tid] = strip_two(x0 + it * BLOCK + tid);
+      if (tid == 0) sh.tile[T] = strip_two(x0 + T);
       // dres[d] = x0 mod q_d, advanced by T mod q_d from tile to tile.
       if (static_cast<uint32_t>(tid) < nd) {
         const uint32_t qd = sh.dq[tid];
