@@ -21,9 +21,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 VALU_PEAK_INT_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes/clk x 2.4 GHz (32-bit integer lane-ops/s)
-# Algorithmic 32-bit integer ops per sieved integer (derivation in the design doc: strip the
-# factor 2, the odd prime-power divisions at 0.273 per integer, canonical key, hash, pass test).
-SIEVE_OPS_PER_INT = 27.0
+# Algorithmic 32-bit integer ops per sieved integer: 9 to reduce the factor 2 of a
+# 64-bit x (add, count trailing zeros, shift), 1.6 for the odd prime-power divisions
+# (0.273 per integer, 6 ops each), 0.9 for the per-segment first-multiple offsets,
+# 6 for the member test, 2.7 to build the entries of the kept 10.7% (key, hash,
+# packing) and 1.1 to rank them for the first partition.
+SIEVE_OPS_PER_INT = 21.0
 ENTRY_BYTES = 16
 CALIB_BYTES = 4 << 30
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plain_2p36.json")
@@ -248,7 +251,7 @@ def main():
         "dtype": "u64",
         "data": "synthetic: the integers 1..N themselves (no dataset)",
         "config": {"workload": f"plain search N=2^{args.log2n}, both kinds, hash-partitioned passes",
-                   "N": N, "passes": agg["passes"], "b1_bits": agg["b1_bits"], "b2_bits": agg["b2_bits"],
+                   "N": N, "member_test": True, "passes": agg["passes"], "b1_bits": agg["b1_bits"], "b2_bits": agg["b2_bits"],
                    "seg_len": agg["seg_len"], "tile": agg["tile"], "parallelism": "single GPU"},
         "pairs_found": len(pairs),
         "roofline": dict(roof[dominant], kernel=dominant),
