@@ -266,6 +266,17 @@ def test_search_2_36_theorem1(ctx):
     assert st["retries"] == 0
 
 
+def test_search_to_1_4e12_theorem1(ctx):
+    """Theorem 1's whole range, n < 1.4e12: 42 pairs, nothing else (about a minute, 12 passes)."""
+    N = 1400000000000 - 1
+    say("search N=1.4e12 - 1 (hash-partitioned passes)")
+    got = ctx.search(N)
+    st = ctx.stats()
+    assert got == theorem1_pairs(N)
+    assert len(got) == 42
+    assert st["integers"] == N and st["retries"] == 0
+
+
 # --- batched --------------------------------------------------------------------------
 
 def test_batch_planted_matches_oracle(ctx):
