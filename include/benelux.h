@@ -39,11 +39,15 @@ extern "C" {
 
 #define BX_VALUE_LIMIT (1ull << 42)
 
-enum { BX_FIRST = 1, BX_SECOND = 2, BX_BOTH = 3 };
+/* kinds: a bit mask.  BX_THIRD adds Erdős's third condition (the problem in
+ * the paper's abstract and introduction): a first-kind pair with also
+ * rad(m+2) = rad(n+2) is reported with kind = 1 | BX_THIRD = 5.  kinds =
+ * BX_THIRD alone reports only such pairs; it needs b + 1 <= hi_max. */
+enum { BX_FIRST = 1, BX_SECOND = 2, BX_BOTH = 3, BX_THIRD = 4 };
 
 enum {
   BX_OK = 0,
-  BX_EINVAL = -1,    /* bad argument: lo = 0, hi < lo, kinds not in {1,2,3}, NULL pointer */
+  BX_EINVAL = -1,    /* bad argument: lo = 0, hi < lo, kinds not in 1..7, NULL pointer  */
   BX_ERANGE = -2,    /* a value needs a radical beyond hi_max or BX_VALUE_LIMIT         */
   BX_ENOMEM = -3,    /* host or device allocation failed, or the HBM budget is too small */
   BX_EDEVICE = -4,   /* a HIP runtime error; the message names it                       */
@@ -51,7 +55,8 @@ enum {
   BX_EINTERNAL = -6  /* a device-side consistency check failed (see bx_last_error)     */
 };
 
-/* One reported pair.  kind is 1 or 2; query is the index of the range query it
+/* One reported pair.  kind is 1 or 2, or 5 (first kind and third condition)
+ * when BX_THIRD is asked for; query is the index of the range query it
  * belongs to (0 for single-range calls). */
 typedef struct {
   uint64_t m;

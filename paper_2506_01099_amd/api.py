@@ -10,7 +10,7 @@ import numpy as np
 
 from ._lib import Pair, Stats, check, load
 
-FIRST, SECOND, BOTH = 1, 2, 3
+FIRST, SECOND, BOTH, THIRD = 1, 2, 3, 4  # THIRD: also rad(m+2) = rad(n+2) (kind 5)
 VALUE_LIMIT = 1 << 42
 
 

@@ -545,8 +545,10 @@ SieveParams base_sieve_params(bx_ctx* c, const Segs& s) {
   return P;
 }
 
-int check_query(const bx_ctx* c, uint64_t a, uint64_t b) {
-  if (b > c->hi_max || b >= BX_VALUE_LIMIT)
+int check_query(const bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds) {
+  // The third condition needs rad(n + 2) <= hi_max + 1 by trial division.
+  const uint64_t top = (kinds & BX_THIRD) ? b + 1 : b;
+  if (top > c->hi_max || top >= BX_VALUE_LIMIT)
     return fail(BX_ERANGE, "range end " + std::to_string(b) + " exceeds hi_max " + std::to_string(c->hi_max));
   (void)a;
   return BX_OK;
@@ -999,7 +1001,9 @@ void serve_worker(bx_ctx::Server* S, int lane) {
     {
       std::lock_guard<std::mutex> lk(c->mu);
       reset_stats(c);
-      rc = run_search(c, s, 1, BX_BOTH, &res, c->graph_batch != 0);
+      uint32_t kall = 0;  // every kind any request of the batch asks for
+      for (uint32_t k : kinds) kall |= k;
+      rc = run_search(c, s, 1, kall, &res, c->graph_batch != 0);
       (void)hipStreamSynchronize(c->stream);
       collect_timings(c);
     }
@@ -1014,7 +1018,9 @@ void serve_worker(bx_ctx::Server* S, int lane) {
       }
       for (const auto& p : res) {
         auto& r = *S->reqs[batch[p.query]];
-        if (r.kinds & p.kind) r.pairs.push_back(OutPair{p.m, p.n, p.kind, 0});
+        const uint32_t base = p.kind & BX_BOTH;
+        const bool three = (r.kinds & BX_THIRD) && (p.kind & BX_THIRD);
+        if ((r.kinds & base) || three) r.pairs.push_back(OutPair{p.m, p.n, three ? p.kind : base, 0});
       }
       S->inflight_bytes -= bytes;
       S->inflight--;
@@ -1134,7 +1140,7 @@ int bx_radical_segment(bx_ctx* c, uint64_t lo, uint64_t hi, uint64_t* out) {
   std::lock_guard<std::mutex> lk(c->mu);
   const double t0 = now_s();
   reset_stats(c);
-  int rc = check_query(c, lo, hi);
+  int rc = check_query(c, lo, hi, 0);
   if (rc != BX_OK) return rc;
   if (hi == lo) return BX_OK;
   BX_HIP(hipSetDevice(c->device));
@@ -1156,7 +1162,7 @@ int bx_radical_segment_dev(bx_ctx* c, uint64_t lo, uint64_t hi, uint64_t* dev_ou
   if (hi > lo && !dev_out) return fail(BX_EINVAL, "dev_out is NULL");
   std::lock_guard<std::mutex> lk(c->mu);
   reset_stats(c);
-  int rc = check_query(c, lo, hi);
+  int rc = check_query(c, lo, hi, 0);
   if (rc != BX_OK) return rc;
   if (hi == lo) return BX_OK;
   BX_HIP(hipSetDevice(c->device));
@@ -1173,13 +1179,13 @@ int bx_search_range(bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds, bx_pair**
   if (!c || !out || !count) return fail(BX_EINVAL, "NULL argument");
   *out = nullptr;
   *count = 0;
-  if (kinds < 1 || kinds > 3) return fail(BX_EINVAL, "kinds must be 1, 2 or 3");
+  if (kinds < 1 || kinds > 7) return fail(BX_EINVAL, "kinds must be a mask in 1..7");
   std::lock_guard<std::mutex> lk(c->mu);
   const double t0 = now_s();
   reset_stats(c);
   if (a == 0) a = 1;
   if (b <= a + 1) return BX_OK;
-  int rc = check_query(c, a, b);
+  int rc = check_query(c, a, b, kinds);
   if (rc != BX_OK) return rc;
   BX_HIP(hipSetDevice(c->device));
   Segs s;
@@ -1202,7 +1208,7 @@ int bx_search_batch(bx_ctx* c, const uint64_t* a, const uint64_t* b, size_t q, u
                     size_t* offsets) {
   if (!c || !out || !offsets || (q && (!a || !b))) return fail(BX_EINVAL, "NULL argument");
   *out = nullptr;
-  if (kinds < 1 || kinds > 3) return fail(BX_EINVAL, "kinds must be 1, 2 or 3");
+  if (kinds < 1 || kinds > 7) return fail(BX_EINVAL, "kinds must be a mask in 1..7");
   if (q > kMaxQueries) return fail(BX_EINVAL, "at most 32768 queries per batch");
   std::lock_guard<std::mutex> lk(c->mu);
   const double t0 = now_s();
@@ -1213,7 +1219,7 @@ int bx_search_batch(bx_ctx* c, const uint64_t* a, const uint64_t* b, size_t q, u
     if (bi < ai) bi = ai;
     if (bi - ai > kMaxQueryLen) return fail(BX_EINVAL, "query longer than 2^28");
     if (bi > ai + 1) {
-      int rc = check_query(c, ai, bi);
+      int rc = check_query(c, ai, bi, kinds);
       if (rc != BX_OK) return rc;
     } else {
       bi = ai;  // fewer than two integers: no pair, no work
@@ -1281,12 +1287,12 @@ int bx_serve_stop(bx_ctx* c) {
 int bx_submit(bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds, uint64_t* ticket) {
   if (!c || !ticket) return fail(BX_EINVAL, "NULL argument");
   if (!c->server) return fail(BX_EINVAL, "server not started");
-  if (kinds < 1 || kinds > 3) return fail(BX_EINVAL, "kinds must be 1, 2 or 3");
+  if (kinds < 1 || kinds > 7) return fail(BX_EINVAL, "kinds must be a mask in 1..7");
   if (a == 0) a = 1;
   if (b < a) b = a;
   if (b - a > kMaxQueryLen) return fail(BX_EINVAL, "request longer than 2^28");
   if (b > a + 1) {
-    int rc = check_query(c, a, b);
+    int rc = check_query(c, a, b, kinds);
     if (rc != BX_OK) return rc;
   }
   auto* S = c->server.get();
@@ -1365,7 +1371,7 @@ int bx_autotune(bx_ctx* c, const uint64_t* a, const uint64_t* b, size_t q, int r
             const uint64_t ai = a[i] == 0 ? 1 : a[i];
             uint64_t bi = b[i] < ai ? ai : b[i];
             if (bi - ai > kMaxQueryLen) rc = fail(BX_EINVAL, "query longer than 2^28");
-            if (bi > ai + 1 && rc == BX_OK) rc = check_query(c, ai, bi);
+            if (bi > ai + 1 && rc == BX_OK) rc = check_query(c, ai, bi, BX_BOTH);
             if (bi <= ai + 1) bi = ai;
             s.q.push_back(Query{ai, bi});
           }

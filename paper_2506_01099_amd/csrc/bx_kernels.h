@@ -29,6 +29,7 @@ constexpr int hit_cap() { return T >= 4096 ? 2048 : 1024; }
 constexpr int kB1Max = 1024;       // first partition fan-out
 constexpr int kB2Max = 4096;       // second partition fan-out
 constexpr int kPartChunk = 4096;   // entries per workgroup in k_partition
+constexpr uint32_t kKindThird = 4; // kinds bit: also test rad(m + 2) = rad(n + 2)
 constexpr int kStageMarginDiv = 4; // the stage is written out once less than T/4 is free
 constexpr int kJoinCap = 8192;     // entries of one LDS join chunk (held in registers)
 constexpr int kJoinSlots = 16384;  // LDS hash-table slots (load <= 0.5)
@@ -642,78 +643,86 @@ struct VerifyParams {
 // every prime <= sqrt(v) being 1 or one more prime.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_verify(VerifyParams P) {
-  __shared__ uint64_t red_r[4][BLOCK], red_s[4][BLOCK];
+  constexpr int NV = 6;  // m, m+1, n, n+1 and, for the third condition, m+2, n+2
+  __shared__ uint64_t red_r[NV][BLOCK], red_s[NV][BLOCK];
   const int tid = threadIdx.x;
   const uint32_t n_cand = min(*P.n_cand, P.cand_cap);
+  const bool third = (P.kinds & kKindThird) != 0;
+  const int nv = third ? NV : 4;
   for (uint32_t c = blockIdx.x; c < n_cand; c += gridDim.x) {
-  __syncthreads();
-  const Cand cd = P.cand[c];
-  const uint32_t qa_idx = entry_grp(cd.a, P.batch ? kGrpMask : 0u);
-  const uint64_t off = P.batch ? P.queries[qa_idx].a : 0ull;
-  const uint64_t xa = entry_pos(cd.a, P.batch) + off, xb = entry_pos(cd.b, P.batch) + off;
-  const uint64_t m = xa < xb ? xa : xb, n = xa < xb ? xb : xa;
-  const uint64_t v[4] = {m, m + 1, n, n + 1};
-  uint64_t pr[4] = {1, 1, 1, 1}, sm[4] = {1, 1, 1, 1};
-  for (uint32_t i = tid; i < P.n_primes; i += BLOCK) {
-    const uint64_t p = P.primes[i];
-    if (p * p > n + 1) break;
+    __syncthreads();
+    const Cand cd = P.cand[c];
+    const uint32_t qa_idx = entry_grp(cd.a, P.batch ? kGrpMask : 0u);
+    const uint64_t off = P.batch ? P.queries[qa_idx].a : 0ull;
+    const uint64_t xa = entry_pos(cd.a, P.batch) + off, xb = entry_pos(cd.b, P.batch) + off;
+    const uint64_t m = xa < xb ? xa : xb, n = xa < xb ? xb : xa;
+    const uint64_t v[NV] = {m, m + 1, n, n + 1, m + 2, n + 2};
+    const uint64_t vmax = third ? n + 2 : n + 1;
+    uint64_t pr[NV] = {1, 1, 1, 1, 1, 1}, sm[NV] = {1, 1, 1, 1, 1, 1};
+    for (uint32_t i = tid; i < P.n_primes; i += BLOCK) {
+      const uint64_t p = P.primes[i];
+      if (p * p > vmax) break;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (p * p <= v[k] && v[k] % p == 0) {
-        pr[k] *= p;
-        uint64_t t = v[k], pk = 1;
-        while (t % p == 0) {
-          t /= p;
-          pk *= p;
+      for (int k = 0; k < NV; ++k) {
+        if (k < nv && p * p <= v[k] && v[k] % p == 0) {
+          pr[k] *= p;
+          uint64_t t = v[k], pk = 1;
+          while (t % p == 0) {
+            t /= p;
+            pk *= p;
+          }
+          sm[k] *= pk;
         }
-        sm[k] *= pk;
       }
     }
-  }
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    red_r[k][tid] = pr[k];
-    red_s[k][tid] = sm[k];
-  }
-  __syncthreads();
-  for (int w = BLOCK / 2; w > 0; w >>= 1) {
-    if (tid < w) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        red_r[k][tid] *= red_r[k][tid + w];
-        red_s[k][tid] *= red_s[k][tid + w];
-      }
+    for (int k = 0; k < NV; ++k) {
+      red_r[k][tid] = pr[k];
+      red_s[k][tid] = sm[k];
     }
     __syncthreads();
-  }
-  if (tid == 0) {
-    uint64_t rad[4];
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+      if (tid < w) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint64_t cof = v[k] / red_s[k][0];
-      rad[k] = red_r[k][0] * (cof > 1 ? cof : 1);
+        for (int k = 0; k < NV; ++k) {
+          red_r[k][tid] *= red_r[k][tid + w];
+          red_s[k][tid] *= red_s[k][tid + w];
+        }
+      }
+      __syncthreads();
     }
-    const uint64_t lo_m = rad[0] < rad[1] ? rad[0] : rad[1], hi_m = rad[0] < rad[1] ? rad[1] : rad[0];
-    const uint64_t lo_n = rad[2] < rad[3] ? rad[2] : rad[3], hi_n = rad[2] < rad[3] ? rad[3] : rad[2];
-    const bool same = (lo_m == lo_n) && (hi_m == hi_n) && m != n;
-    const bool matches_key = lo_m == entry_lo(cd.a) && hi_m == entry_hi(cd.a);
-    if (!same || !matches_key) {
-      atomicAdd(&P.flags[kFlagVerifyFail], 1u);
-    } else {
-      const uint32_t kind = rad[0] == rad[2] ? 1u : 2u;
-      if (P.kinds & kind) {
-        const uint32_t k = atomicAdd(&P.flags[kFlagOut], 1u);
-        if (k < P.out_cap) {
-          OutPair o;
-          o.m = m;
-          o.n = n;
-          o.kind = kind;
-          o.query = P.batch ? qa_idx : 0u;
-          P.out[k] = o;
+    if (tid == 0) {
+      uint64_t rad[NV];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        const uint64_t cof = v[k] / red_s[k][0];
+        rad[k] = red_r[k][0] * (cof > 1 ? cof : 1);
+      }
+      const uint64_t lo_m = rad[0] < rad[1] ? rad[0] : rad[1], hi_m = rad[0] < rad[1] ? rad[1] : rad[0];
+      const uint64_t lo_n = rad[2] < rad[3] ? rad[2] : rad[3], hi_n = rad[2] < rad[3] ? rad[3] : rad[2];
+      const bool same = (lo_m == lo_n) && (hi_m == hi_n) && m != n;
+      const bool matches_key = lo_m == entry_lo(cd.a) && hi_m == entry_hi(cd.a);
+      if (!same || !matches_key) {
+        atomicAdd(&P.flags[kFlagVerifyFail], 1u);
+      } else {
+        // Kind 1 iff rad(m) = rad(n) (Algorithm 2); the third-condition bit
+        // marks a first-kind pair with rad(m + 2) = rad(n + 2) as well.
+        const uint32_t base = rad[0] == rad[2] ? 1u : 2u;
+        const bool three = third && base == 1u && rad[4] == rad[5];
+        const uint32_t kind = base | (three ? kKindThird : 0u);
+        if ((P.kinds & base) || three) {
+          const uint32_t k = atomicAdd(&P.flags[kFlagOut], 1u);
+          if (k < P.out_cap) {
+            OutPair o;
+            o.m = m;
+            o.n = n;
+            o.kind = kind;
+            o.query = P.batch ? qa_idx : 0u;
+            P.out[k] = o;
+          }
         }
       }
     }
-  }
   }
 }
 

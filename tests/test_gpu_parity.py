@@ -177,6 +177,18 @@ def test_kinds_filter(ctx, kinds):
     assert ctx.search(1 << 20, kinds) == oracle.search(1 << 20, kinds)
 
 
+def test_third_condition(ctx):
+    """Erdős's third condition rad(m+2) = rad(n+2): no pair up to 2^28 meets it (none is
+    known), so the lists with the bit equal the oracle's and the bit alone gives nothing.
+    The branch that marks a pair (kind 5) has no known input: parity unpinned."""
+    N = 1 << 28
+    assert ctx.search(N, 7) == ctx.search(N, 3) == theorem1_pairs(N)
+    assert ctx.search(N, 4) == []
+    assert ctx.search(1 << 20, 5) == oracle.search(1 << 20, 1)
+    got = ctx.search_batch(np.array([1, 70], dtype=np.uint64), np.array([1 << 20, 1300], dtype=np.uint64), 7)
+    assert got == [oracle.search_range(1, 1 << 20), oracle.search_range(70, 1300)]
+
+
 @pytest.mark.parametrize("passes", [1, 2, 3, 5, 7, 16, 64])
 def test_pass_count_invariance(ctx, passes):
     ctx.set_option("passes", passes)

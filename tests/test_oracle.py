@@ -231,3 +231,22 @@ def test_bad_arguments():
         oracle.radicals(0, 10)
     assert oracle.search_range(5, 5) == []
     assert oracle.search(1) == []
+
+
+# --- Erdős's third condition (abstract, introduction) -------------------------------------
+
+def test_no_listed_first_kind_pair_meets_the_third_condition():
+    """The paper's argument for the family: m + 2 = 2^(k+1) is a power of two while
+    n + 2 = (2^k - 1) 2^(k+2) + 2 is 2 mod 4, so rad(m+2) = 2 != rad(n+2); and for the
+    exceptional pair m + 2 = 77 = 7 * 11 while n + 2 = 1217 is prime.  Checked with the
+    oracle's radicals for every first-kind pair with n < 1.4e12."""
+    for m, n, kind in theorem1_pairs(THEOREM1_LIMIT - 1):
+        if kind != 1:
+            continue
+        if (m, n) == (75, 1215):
+            assert oracle.rad(m + 2) == 77 and oracle.rad(n + 2) == 1217
+        else:
+            k = (m + 2).bit_length() - 1
+            assert m + 2 == 2 ** k and (n + 2) % 4 == 2
+            assert oracle.rad(m + 2) == 2 and oracle.rad(n + 2) != 2
+        assert oracle.rad(m + 2) != oracle.rad(n + 2)
