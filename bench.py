@@ -27,7 +27,7 @@ VALU_PEAK_INT_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes/clk x 2.4 GHz (32-bit
 # 6 for the member test, 2.7 to build the entries of the kept 10.7% (key, hash,
 # packing) and 1.1 to rank them for the first partition.
 SIEVE_OPS_PER_INT = 21.0
-ENTRY_BYTES = 16
+ENTRY_BYTES = 12
 CALIB_BYTES = 4 << 30
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plain_2p36.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2506_01099_amd", "csrc", f) for f in ("bx_kernels.h", "bx_device.h")]

@@ -161,7 +161,7 @@ int bx_get_stats(bx_ctx* ctx, bx_stats* out);
  *   "timing"       1 = record HIP events per kernel (default 1)
  *   "verify"       1 = recompute every candidate by trial division (default 1)
  *   "b1_bits"      force the first partition fan-out (0 = plan)
- *   "b2_bits"      force the second partition fan-out (0 = plan)
+ *   "b2_bits"      force the second partition fan-out, <= 11 (0 = plan)
  *   "group"        first-level buckets per second-level launch (1, 2, 4, 8; 0 = 8)
  *   "tile"         sieve LDS tile: 2048 (two workgroups per CU) or 4096 (one; 0 = 4096)
  *   "graph"        1 = batched calls run as one captured HIP graph (default 1)

@@ -331,7 +331,7 @@ int make_plan(bx_ctx* c, uint64_t n_keys, uint64_t n_expect, uint64_t share, uin
     // they stay within one LDS join chunk (8192 entries).
     uint32_t b2 = bucket * 1.03 > 7600.0 ? ceil_log2(bucket * 1.03 / 7600.0) : 0;
     if (c->force_b2 >= 0) b2 = static_cast<uint32_t>(c->force_b2);
-    if (b2 > 12 || b1 + b2 > 32) {
+    if (b2 > 11 || b1 + b2 > 32) {
       if (c->force_passes > 0) return fail(BX_ENOMEM, "forced pass count leaves partitions too large");
       continue;
     }
@@ -574,7 +574,6 @@ struct Job {
   uint32_t sieve_grid = 0, B1 = 1, B2 = 1, G = 1, cpr = 1;
   uint64_t ngsub = 1, n_regions = 1, part_grid = 8;
   uint32_t gmask = 0;
-  uint64_t kmask1 = 0;
 };
 
 int prepare_job(bx_ctx* c, Segs& s, int batch, uint32_t kinds, hipStream_t st, Job* j) {
@@ -594,13 +593,12 @@ int prepare_job(bx_ctx* c, Segs& s, int batch, uint32_t kinds, hipStream_t st, J
   j->n_regions = static_cast<uint64_t>(j->B1) * j->sieve_grid;
   j->cpr = static_cast<uint32_t>((plan.cap1 + kPartChunk - 1) / kPartChunk);
   const uint64_t chunks = static_cast<uint64_t>(j->sieve_grid) * j->cpr;  // per bucket
-  // Persistent partition grid: one workgroup per CU (LDS bound), a multiple
+  // Persistent partition grid: one workgroup per CU (measured faster than two), a multiple
   // of 8 so that every XCD serves its share of the group's buckets.
   const uint64_t per = 8 / j->G;
   j->part_grid = 8ull * std::min<uint64_t>(std::max(1, c->n_cu / 8), (chunks + per - 1) / per);
   if (j->part_grid > 0x7FFFFFFFull) return fail(BX_EINTERNAL, "partition grid too large");
   j->gmask = batch ? kGrpMask : 0u;
-  j->kmask1 = kM42 | (static_cast<uint64_t>(j->gmask) << kGrpShift);
   if ((rc = ensure(c, c->l1, j->n_regions * plan.cap1 * sizeof(Entry))) != BX_OK) return rc;
   if ((rc = ensure(c, c->l2, j->ngsub * plan.cap2 * sizeof(Entry))) != BX_OK) return rc;
   if ((rc = ensure(c, c->cnt1, j->n_regions * 4ull)) != BX_OK) return rc;
@@ -639,7 +637,6 @@ int enqueue_pass(bx_ctx* c, const Job& j, uint64_t ph_lo, uint64_t ph_hi, hipStr
   P.pfilter = !(ph_lo == 0 && ph_hi == (1ull << 32));
   P.ph_lo = ph_lo;
   P.ph_hi = ph_hi;
-  P.b1shift = plan.b1bits ? 32 - plan.b1bits : 0;
   P.b1mask = j.B1 - 1;
   P.l1 = static_cast<Entry*>(c->l1.p);
   P.cap1 = plan.cap1;
@@ -664,7 +661,7 @@ int enqueue_pass(bx_ctx* c, const Job& j, uint64_t ph_lo, uint64_t ph_hi, hipStr
     Q.l2 = static_cast<Entry*>(c->l2.p);
     Q.cap2 = plan.cap2;
     Q.cnt2 = static_cast<uint32_t*>(c->cnt2.p);
-    Q.b2shift = plan.b2bits ? 32 - plan.b1bits - plan.b2bits : 0;
+    Q.b2shift = plan.b2bits ? kFpBits - plan.b2bits : 0;
     Q.b2mask = j.B2 - 1;
     Q.gmask = j.gmask;
     Q.flags = d_flags;
@@ -678,7 +675,6 @@ int enqueue_pass(bx_ctx* c, const Job& j, uint64_t ph_lo, uint64_t ph_hi, hipStr
     J.cap2 = plan.cap2;
     J.cnt2 = static_cast<uint32_t*>(c->cnt2.p);
     J.n_sub = j.ngsub;
-    J.kmask1 = j.kmask1;
     J.gmask = j.gmask;
     J.cand = static_cast<Cand*>(c->cand.p);
     J.cand_cap = kCandCap;
@@ -1118,7 +1114,7 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
     if (v > 10) return fail(BX_EINVAL, "b1_bits <= 10");
     c->force_b1 = v == 0 ? -1 : static_cast<int>(v);
   } else if (n == "b2_bits") {
-    if (v > 12) return fail(BX_EINVAL, "b2_bits <= 12");
+    if (v > 11) return fail(BX_EINVAL, "b2_bits <= 11");
     c->force_b2 = v == 0 ? -1 : static_cast<int>(v);
   } else {
     return fail(BX_EINVAL, "unknown option " + n);

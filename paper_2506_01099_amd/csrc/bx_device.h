@@ -1,14 +1,15 @@
 // Device-side building blocks of the Benelux-pair search (gfx950).
 //
 // Layouts shared by the kernels:
-//   Entry (16 B): the exact set S_x = {rad(x), rad(x+1)} of one integer x, with
-//   the position of x, packed into two 64-bit words:
-//     w0 = lo | (pos[0:22) << 42)
-//     w1 = hi | (pos[22:..) << 42) | (grp << 48) | (orient << 63)
-//   lo < hi are the two radicals (each below 2^42), orient = 1 when
-//   rad(x) = hi.  Single-range calls store pos = x (43 bits, grp absent);
-//   batched calls store pos = x - a_query (28 bits) and grp = query (15 bits).
-//   The join key is (lo, hi) plus grp in batched mode.
+//   Entry (12 B): one integer x that entered the join, as three 32-bit words
+//     w0 = pos[0:32), w1 = pos[32:43) | fp[0:21) << 11, w2 = fp[21:53).
+//   pos (43 bits) is x in single-range calls; in batched calls it is
+//   x - a_query (28 bits) with the query index in bits 28..42.  fp (53 bits)
+//   is a fingerprint of the set S_x = {rad(x), rad(x+1)} (and of the query in
+//   batched calls): bits 11..63 of key64 of the canonical pair lo < hi.
+//   Equal sets have equal fingerprints, so the join never misses a pair;
+//   equal fingerprints of different sets are dropped by the verification,
+//   which recomputes the four radicals by trial division.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -16,12 +17,12 @@
 
 namespace bx {
 
-constexpr uint64_t kM42 = (1ull << 42) - 1;
-constexpr uint32_t kGrpShift = 48;
+constexpr uint32_t kGrpShift = 28;    // query id position inside pos (batched mode)
 constexpr uint32_t kGrpMask = 0x7FFF;  // 15-bit query id in batched mode
+constexpr uint32_t kFpBits = 53;
 
 struct Entry {
-  uint64_t w0, w1;
+  uint32_t w0, w1, w2;
 };
 
 // Odd prime power q = p^k (k >= 2) with its reciprocal (for q | x tests and the
@@ -65,6 +66,7 @@ enum : int {
   kFlagOut = 3,
   kFlagVerifyFail = 4,
   kFlagSpillOverflow = 5,
+  kFlagFalseCand = 6,  // equal fingerprints of different sets (dropped)
   kFlagCount = 8
 };
 
@@ -144,16 +146,6 @@ __device__ __forceinline__ bool may_pair(uint64_t x, uint64_t r0, uint64_t r1, u
   return true;
 }
 
-// Murmur3's 32-bit finalizer (Appleby): a bijective avalanche mix.
-__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
-  h ^= h >> 16;
-  h *= 0x85EBCA6Bu;
-  h ^= h >> 13;
-  h *= 0xC2B2AE35u;
-  h ^= h >> 16;
-  return h;
-}
-
 // Cheap hash of a join key, evaluated for every x to pick its pass: 21-bit
 // limbs through full-rate 24-bit multiplies, then one xorshift-multiply round.
 // Any function of the key gives exact passes; this one only has to spread the
@@ -169,36 +161,46 @@ __device__ __forceinline__ uint32_t pass_hash(uint64_t lo, uint64_t hi, uint32_t
   return s;
 }
 
-// Hash of a join key (lo, hi, grp) for the partition bits.  The key is
-// canonical (lo < hi), so the hash is the same for both orders of the set.
-__device__ __forceinline__ uint32_t key_hash(uint64_t lo, uint64_t hi, uint32_t grp) {
-  const uint32_t c = (static_cast<uint32_t>(lo >> 32) | (static_cast<uint32_t>(hi >> 32) << 10)) + grp * 0x01000193u;
-  return fmix32(static_cast<uint32_t>(lo) ^ fmix32(static_cast<uint32_t>(hi) ^ (c * 0x9E3779B1u)));
+// SplitMix64's output mix (Steele, Lea & Flood 2014): a bijection of 64-bit words.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z ^= z >> 30;
+  z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 27;
+  z *= 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return z;
 }
 
-// An independent hash of the same key for the slots of the LDS join table.
-__device__ __forceinline__ uint32_t key_hash2(uint64_t lo, uint64_t hi, uint32_t grp) {
-  const uint32_t c = (static_cast<uint32_t>(lo >> 32) | (static_cast<uint32_t>(hi >> 32) << 10)) ^ (grp * 0x27D4EB2Fu);
-  return fmix32(static_cast<uint32_t>(hi) ^ fmix32((static_cast<uint32_t>(lo) + 0x7F4A7C15u) ^ (c * 0x85EBCA77u)));
+// 64-bit hash of a join key: the canonical pair lo < hi (each below 2^43)
+// and, in batched mode, the query id.  Bits 0..10 pick the first-level
+// bucket, bits 11..63 are the entry's fingerprint (whose top bits pick the
+// second-level partition and whose low bits the LDS table slot).
+__device__ __forceinline__ uint64_t key64(uint64_t lo, uint64_t hi, uint32_t grp) {
+  return mix64((lo | (static_cast<uint64_t>(grp) << 43)) + mix64(hi ^ 0x9E3779B97F4A7C15ull));
 }
 
-__device__ __forceinline__ uint64_t entry_lo(const Entry& e) { return e.w0 & kM42; }
-__device__ __forceinline__ uint64_t entry_hi(const Entry& e) { return e.w1 & kM42; }
+__device__ __forceinline__ uint64_t entry_pos43(const Entry& e) {
+  return e.w0 | (static_cast<uint64_t>(e.w1 & 0x7FFu) << 32);
+}
+__device__ __forceinline__ uint64_t entry_fp(const Entry& e) {
+  return (e.w1 >> 11) | (static_cast<uint64_t>(e.w2) << 21);
+}
 __device__ __forceinline__ uint32_t entry_grp(const Entry& e, uint32_t gmask) {
-  return static_cast<uint32_t>(e.w1 >> kGrpShift) & gmask;
+  return static_cast<uint32_t>(entry_pos43(e) >> kGrpShift) & gmask;
 }
 
 // Position stored in an entry: plain mode x (43 bits), batched mode x - a (28 bits).
 __device__ __forceinline__ uint64_t entry_pos(const Entry& e, int batch) {
-  const uint64_t low = e.w0 >> 42;
-  const uint64_t high = (e.w1 >> 42) & (batch ? 0x3Full : 0x1FFFFFull);
-  return low | (high << 22);
+  const uint64_t p = entry_pos43(e);
+  return batch ? (p & ((1ull << kGrpShift) - 1)) : p;
 }
 
-__device__ __forceinline__ Entry make_entry(uint64_t lo, uint64_t hi, uint64_t pos, uint32_t grp, uint32_t orient) {
+// pos43 as described above; fp53 = key64(...) >> 11.
+__device__ __forceinline__ Entry make_entry(uint64_t pos43, uint64_t fp53) {
   Entry e;
-  e.w0 = lo | (pos << 42);
-  e.w1 = hi | ((pos >> 22) << 42) | (static_cast<uint64_t>(grp) << kGrpShift) | (static_cast<uint64_t>(orient) << 63);
+  e.w0 = static_cast<uint32_t>(pos43);
+  e.w1 = static_cast<uint32_t>(pos43 >> 32) | (static_cast<uint32_t>(fp53) << 11);
+  e.w2 = static_cast<uint32_t>(fp53 >> 21);
   return e;
 }
 

@@ -27,7 +27,7 @@ constexpr int MODE_KEYS = 1;
 template <int T>
 constexpr int hit_cap() { return T >= 4096 ? 2048 : 1024; }
 constexpr int kB1Max = 1024;       // first partition fan-out
-constexpr int kB2Max = 4096;       // second partition fan-out
+constexpr int kB2Max = 2048;       // second partition fan-out
 constexpr int kPartChunk = 4096;   // entries per workgroup in k_partition
 constexpr uint32_t kKindThird = 4; // kinds bit: also test rad(m + 2) = rad(n + 2)
 constexpr int kStageMarginDiv = 4; // the stage is written out once less than T/4 is free
@@ -56,7 +56,7 @@ struct SieveParams {
   uint32_t prune;         // drop x that cannot be a member of any pair (may_pair)
   uint32_t pfilter;       // keep x only when pass_hash(key) is in [ph_lo, ph_hi)
   uint64_t ph_lo, ph_hi;
-  uint32_t b1shift, b1mask;
+  uint32_t b1mask;  // first-level bucket = low bits of key64
   Entry* l1;       // region (b, w) of bucket b written by workgroup w: l1 + (b * gridDim.x + w) * cap1
   uint64_t cap1;   // entries per region
   uint32_t* cnt1;  // B1 x gridDim.x fill counts, written at the end of the kernel
@@ -96,15 +96,15 @@ struct SieveShSel<T, BLOCK, MODE_KEYS> {
 // bucket b: shared by all workgroups (global, one atomic per non-empty bucket)
 // or, with PRIVATE, owned by this workgroup (no atomics).  dst(b, k) stores the
 // k-th entry of the bucket (k < cap).
-template <int BLOCK, int NB, bool PRIVATE, typename Dst, typename Mid>
-__device__ void scatter_runs(uint32_t n, uint32_t nb, const Entry* ent, const uint16_t* sb, uint16_t* perm,
+template <int BLOCK, int NB, bool PRIVATE, typename Bucket, typename Dst, typename Mid>
+__device__ void scatter_runs(uint32_t n, uint32_t nb, const Entry* ent, Bucket sb, uint16_t* perm,
                              uint32_t* cnt, uint32_t* gofs, uint32_t* wsum, uint32_t* gcur, uint64_t cap,
                              uint32_t* flag, Dst dst, Mid mid) {
   constexpr int BINS = (NB + BLOCK - 1) / BLOCK;
   const int tid = threadIdx.x;
   for (uint32_t b = tid; b < nb; b += BLOCK) cnt[b] = 0;
   __syncthreads();
-  for (uint32_t i = tid; i < n; i += BLOCK) atomicAdd(&cnt[sb[i]], 1u);
+  for (uint32_t i = tid; i < n; i += BLOCK) atomicAdd(&cnt[sb(i)], 1u);
   __syncthreads();
   uint32_t loc[BINS];
   uint32_t sum = 0;
@@ -134,11 +134,11 @@ __device__ void scatter_runs(uint32_t n, uint32_t nb, const Entry* ent, const ui
   }
   __syncthreads();
   mid();  // the global cursors are taken: work that may overlap the scatter
-  for (uint32_t i = tid; i < n; i += BLOCK) perm[atomicAdd(&cnt[sb[i]], 1u)] = static_cast<uint16_t>(i);
+  for (uint32_t i = tid; i < n; i += BLOCK) perm[atomicAdd(&cnt[sb(i)], 1u)] = static_cast<uint16_t>(i);
   __syncthreads();
   for (uint32_t j = tid; j < n; j += BLOCK) {
     const uint32_t i = perm[j];
-    const uint32_t b = sb[i];
+    const uint32_t b = sb(i);
     const uint32_t k = gofs[b] + j;
     if (k < cap)
       dst(b, k, ent[i]);
@@ -154,7 +154,9 @@ __device__ void flush_stage(SieveShKeys<T, BLOCK>& sh, const SieveParams& P) {
   const uint32_t n = min(sh.stage_n, static_cast<uint32_t>(T));  // later slots went straight out
   const uint64_t cap1 = P.cap1, W = gridDim.x;
   Entry* l1 = P.l1 + static_cast<uint64_t>(blockIdx.x) * cap1;
-  scatter_runs<BLOCK, kB1Max, true>(n, P.b1mask + 1, sh.stage, sh.sb, sh.perm, sh.cnt, sh.gofs, sh.wsum, sh.lcur, cap1,
+  const uint16_t* sb = sh.sb;
+  scatter_runs<BLOCK, kB1Max, true>(n, P.b1mask + 1, sh.stage, [=](uint32_t i) -> uint32_t { return sb[i]; }, sh.perm,
+                                    sh.cnt, sh.gofs, sh.wsum, sh.lcur, cap1,
                                     &P.flags[kFlagL1Overflow],
                                     [=](uint32_t b, uint32_t k, const Entry& e) { l1[b * W * cap1 + k] = e; },
                                     [] {});
@@ -402,8 +404,10 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
             const uint64_t a = sh.tile[i], b = sh.tile[i + 1];
             const uint64_t klo = a < b ? a : b, khi = a < b ? b : a;
             const uint64_t x = x0 + i;
-            const Entry e = make_entry(klo, khi, P.batch ? x - qa : x, grp, a > b ? 1u : 0u);
-            const uint32_t bk = (key_hash(klo, khi, grp) >> P.b1shift) & P.b1mask;
+            const uint64_t h = key64(klo, khi, grp);
+            const uint64_t pos43 = P.batch ? ((x - qa) | (static_cast<uint64_t>(grp) << kGrpShift)) : x;
+            const Entry e = make_entry(pos43, h >> 11);
+            const uint32_t bk = static_cast<uint32_t>(h) & P.b1mask;
             const uint32_t slot = sbase + k;
             if (slot < static_cast<uint32_t>(T)) {
               sh.stage[slot] = e;
@@ -439,7 +443,7 @@ struct PartParams {
   Entry* l2;       // group buffer: G x B2 sub-buckets of cap2 entries
   uint32_t cap2;
   uint32_t* cnt2;  // G x B2 cursors (zero on entry)
-  uint32_t b2shift, b2mask;
+  uint32_t b2shift, b2mask;  // second-level partition = top bits of the fingerprint
   uint32_t gmask;
   uint32_t* flags;
 };
@@ -456,7 +460,7 @@ __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
   constexpr int EPT = kPartChunk / BLOCK;
   static_assert(kPartChunk % BLOCK == 0, "chunk shape");
   __shared__ Entry ent[kPartChunk];
-  __shared__ uint16_t sb[kPartChunk], perm[kPartChunk];
+  __shared__ uint16_t sbk[kPartChunk], perm[kPartChunk];
   __shared__ uint32_t cnt[kB2Max], gofs[kB2Max];
   __shared__ uint32_t wsum[BLOCK / 64];
   const int tid = threadIdx.x;
@@ -474,6 +478,8 @@ __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
   Entry* out = P.l2 + static_cast<uint64_t>(gb) * B2 * P.cap2;
   uint32_t* gcur = P.cnt2 + static_cast<uint64_t>(gb) * B2;
   const uint32_t cap2 = P.cap2;
+  // The partition of an entry is the top of its fingerprint.
+  auto bucket_of = [&](uint32_t i) -> uint32_t { return sbk[i]; };
   // Chunk ci of the bucket: entries [s0, s0 + n) of region ci / cpr.
   auto chunk = [&](uint64_t ci, const Entry** src) -> uint32_t {
     const uint64_t region = static_cast<uint64_t>(b1) * P.W + ci / cpr;
@@ -496,8 +502,7 @@ __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
       const uint32_t i = tid + q * BLOCK;
       if (i < n) {
         ent[i] = e[q];
-        const uint32_t h = key_hash(entry_lo(e[q]), entry_hi(e[q]), entry_grp(e[q], P.gmask));
-        sb[i] = static_cast<uint16_t>((h >> P.b2shift) & P.b2mask);
+        sbk[i] = static_cast<uint16_t>(static_cast<uint32_t>(entry_fp(e[q]) >> P.b2shift) & P.b2mask);
       }
     }
     const uint32_t n_cur = n;
@@ -514,7 +519,7 @@ __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
     __syncthreads();
     if (n_cur)  // uniform over the workgroup
       scatter_runs<BLOCK, kB2Max, false>(
-          n_cur, B2, ent, sb, perm, cnt, gofs, wsum, gcur, cap2, &P.flags[kFlagL2Overflow],
+          n_cur, B2, ent, bucket_of, perm, cnt, gofs, wsum, gcur, cap2, &P.flags[kFlagL2Overflow],
           [=](uint32_t b, uint32_t kk, const Entry& x) { out[static_cast<uint64_t>(b) * cap2 + kk] = x; }, prefetch);
     else
       prefetch();
@@ -526,7 +531,6 @@ struct JoinParams {
   uint32_t cap2;
   uint32_t* cnt2;
   uint64_t n_sub;
-  uint64_t kmask1;
   uint32_t gmask;
   Cand* cand;
   uint32_t cand_cap;
@@ -587,8 +591,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
     for (int k = 0; k < EPT; ++k) {
       const uint32_t i = tid + k * BLOCK;
       if (i >= m) continue;
-      const uint64_t k0 = e[k].w0 & kM42, k1 = e[k].w1 & P.kmask1;
-      const uint32_t h = key_hash2(k0, e[k].w1 & kM42, entry_grp(e[k], P.gmask));
+      const uint64_t fk = entry_fp(e[k]);
+      const uint32_t gk = entry_grp(e[k], P.gmask);
+      const uint32_t h = static_cast<uint32_t>(fk);
       const uint32_t mine = (h & ~kIdxMask) | i;
       uint32_t s = h & smask;
       for (;;) {
@@ -599,7 +604,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
         }
         if (((v ^ mine) & ~kIdxMask) == 0) {
           const Entry f = src[i0 + (v & kIdxMask)];
-          if ((f.w0 & kM42) == k0 && (f.w1 & P.kmask1) == k1) emit_cand(P, e[k], f);
+          if (entry_fp(f) == fk && entry_grp(f, P.gmask) == gk) emit_cand(P, e[k], f);
         }
         s = (s + 1) & smask;
       }
@@ -607,15 +612,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
     __syncthreads();
     for (uint32_t jj = i0 + m + tid; jj < n; jj += BLOCK) {
       const Entry g = src[jj];
-      const uint64_t k0 = g.w0 & kM42, k1 = g.w1 & P.kmask1;
-      const uint32_t h = key_hash2(k0, g.w1 & kM42, entry_grp(g, P.gmask));
+      const uint64_t fk = entry_fp(g);
+      const uint32_t gk = entry_grp(g, P.gmask);
+      const uint32_t h = static_cast<uint32_t>(fk);
       uint32_t s = h & smask;
       for (;;) {
         const uint32_t v = table[s];
         if (v == kEmpty) break;
         if (((v ^ h) & ~kIdxMask) == 0) {
           const Entry f = src[i0 + (v & kIdxMask)];
-          if ((f.w0 & kM42) == k0 && (f.w1 & P.kmask1) == k1) emit_cand(P, g, f);
+          if (entry_fp(f) == fk && entry_grp(f, P.gmask) == gk) emit_cand(P, g, f);
         }
         s = (s + 1) & smask;
       }
@@ -701,9 +707,10 @@ __global__ __launch_bounds__(BLOCK) void k_verify(VerifyParams P) {
       const uint64_t lo_m = rad[0] < rad[1] ? rad[0] : rad[1], hi_m = rad[0] < rad[1] ? rad[1] : rad[0];
       const uint64_t lo_n = rad[2] < rad[3] ? rad[2] : rad[3], hi_n = rad[2] < rad[3] ? rad[3] : rad[2];
       const bool same = (lo_m == lo_n) && (hi_m == hi_n) && m != n;
-      const bool matches_key = lo_m == entry_lo(cd.a) && hi_m == entry_hi(cd.a);
-      if (!same || !matches_key) {
-        atomicAdd(&P.flags[kFlagVerifyFail], 1u);
+      if (!same) {
+        atomicAdd(&P.flags[kFlagFalseCand], 1u);  // equal fingerprints, different sets
+      } else if ((key64(lo_m, hi_m, P.batch ? qa_idx : 0u) >> 11) != entry_fp(cd.a)) {
+        atomicAdd(&P.flags[kFlagVerifyFail], 1u);  // the entry does not hold this set's fingerprint
       } else {
         // Kind 1 iff rad(m) = rad(n) (Algorithm 2); the third-condition bit
         // marks a first-kind pair with rad(m + 2) = rad(n + 2) as well.
