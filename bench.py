@@ -266,7 +266,7 @@ def main():
         log("same search without the member test ...")
         bx.set_option("prune", 0)
         try:
-            p0, total0, per0, agg0 = run_plain(bx, N, 1, 0)
+            p0, total0, per0, agg0 = run_plain(bx, N, 1, 1)
         finally:
             bx.set_option("prune", 1)
         if p0 != pairs:
