@@ -189,7 +189,7 @@ def roofline_from(agg, n_ints_per_step, entries_per_step, steps, traffic):
         out["sieve"] = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_INT_OPS / 1e12, "unit": "Tops/s",
                         "frac": ach / (VALU_PEAK_INT_OPS / 1e12), "traffic": traffic.get("sieve"),
                         "avg_launch_ms": avg_ms, "integers_per_launch": ints_per_launch}
-    # Partition: HBM-bound, 16 B read + 16 B write per entry (the entries the
+    # Partition: HBM-bound, 12 B read + 12 B write per entry (the entries the
     # sieve wrote: the integers that pass the member test).
     if ln["partition"]:
         avg_ms = ms["partition"] / ln["partition"]
@@ -206,7 +206,7 @@ def roofline_from(agg, n_ints_per_step, entries_per_step, steps, traffic):
                        "frac": ach / HBM_PEAK_GBS, "traffic": traffic.get("join"), "avg_launch_ms": avg_ms,
                        "bytes_per_launch": b}
     # The join as a whole (second scatter + LDS join): 32 B per key algorithmic
-    # (one 16 B entry written by the sieve, read once), over the join kernels' time.
+    # (one 12 B entry written by the sieve, read once), over the join kernels' time.
     if ln["partition"] and ln["join"]:
         t = (ms["partition"] + ms["join"]) * 1e-3
         ach = 2 * ENTRY_BYTES * entries_per_step * steps / t / 1e9

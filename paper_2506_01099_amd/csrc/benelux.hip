@@ -303,7 +303,7 @@ uint64_t fixed_bytes(const bx_ctx* c, uint32_t sieve_grid) {
 
 // Choose the number of hash passes P (any integer: pass p keeps the keys whose
 // pass hash falls in the p-th of P equal ranges) and the two partition
-// fan-outs.  One pass's entries live in the first-level buckets (16 B each);
+// fan-outs.  One pass's entries live in the first-level buckets (12 B each);
 // the second level only needs a buffer for one group of buckets at a time, so
 // the budget sets P through the first level alone.  Second-level partitions
 // end up near 3800-7600 entries, which one workgroup joins in LDS.

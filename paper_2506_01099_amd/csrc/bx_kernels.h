@@ -1,17 +1,19 @@
 // HIP kernels of the Benelux-pair search for gfx950.
 //
 //   k_sieve<MODE_RAD>   Algorithm 1 on LDS tiles, radicals written to HBM.
-//   k_sieve<MODE_KEYS>  Algorithm 1 on LDS tiles, then the set S_x of every x
-//                       (Section 2.1), the pass filter of the hash-partitioned
-//                       passes, wave-ballot compaction and the first partition
-//                       scatter of the exact join, fused in one kernel.
+//   k_sieve<MODE_KEYS>  Algorithm 1 on LDS tiles, then for every x the member
+//                       test (may_pair), the pass filter of the hash-
+//                       partitioned passes, a fingerprint of the set S_x
+//                       (Section 2.1), wave-ballot compaction and the first
+//                       partition scatter of the join, fused in one kernel.
 //   k_partition         second partition scatter (fan-out B2), XCD-aware.
 //   k_join              LDS hash join of one partition: inserts that detect
-//                       every earlier equal key on their probe chain, as the
-//                       insert step of Algorithm 3 does, so each pair of a
-//                       group of equal sets is reported exactly once.
+//                       every earlier equal fingerprint on their probe chain,
+//                       as the insert step of Algorithm 3 does, so each pair
+//                       of a group of equal sets is reported exactly once.
 //   k_verify            every candidate pair recomputed by trial division with
-//                       the resident primes, classified (first kind when
+//                       the resident primes (equal fingerprints of different
+//                       sets are dropped here), classified (first kind when
 //                       rad(m) = rad(n), Algorithm 2) and filtered by kind.
 //   k_fill_u32          fills a word array (clears counters inside graphs).
 #pragma once
