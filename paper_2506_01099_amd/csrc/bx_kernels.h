@@ -32,7 +32,7 @@ constexpr int kB1Max = 1024;       // first partition fan-out
 constexpr int kB2Max = 2048;       // second partition fan-out
 constexpr int kPartChunk = 4096;   // entries per workgroup in k_partition
 constexpr uint32_t kKindThird = 4; // kinds bit: also test rad(m + 2) = rad(n + 2)
-constexpr int kStageMarginDiv = 4; // the stage is written out once less than T/4 is free
+constexpr int kStageMarginDiv = 4; // the stage is written out once less than T/4 slots are free
 constexpr int kJoinCap = 8192;     // entries of one LDS join chunk (held in registers)
 constexpr int kJoinSlots = 16384;  // LDS hash-table slots (load <= 0.5)
 constexpr int kJoinIdxBits = 14;   // slot = tag (18 bits) << 14 | entry index
@@ -73,12 +73,15 @@ struct SieveShCommon {
   uint32_t wsum[BLOCK / 64];
 };
 
-// The stage holds one tile's worth of entries (a flush happens before a tile
-// whose entries might not fit).
+// The stage collects the kept entries of several tiles; it is written out when
+// less than T / kStageMarginDiv slots are free at the start of a tile.
 template <int T, int BLOCK>
 struct SieveShKeys : SieveShCommon<T, BLOCK> {
-  Entry stage[T];
-  uint16_t sb[T], perm[T];
+  // Stage capacity: 1.5 tiles with the 4096 tile (one workgroup per CU, the
+  // 12 B entries leave room), one tile with the 2048 tile (two per CU).
+  static constexpr int kStage = T >= 4096 ? T + T / 2 : T;
+  Entry stage[kStage];
+  uint16_t sb[kStage], perm[kStage];  // perm also holds the waves' kept lists (T entries)
   uint32_t cnt[kB1Max], gofs[kB1Max], lcur[kB1Max];
 };
 
@@ -153,7 +156,7 @@ __device__ void scatter_runs(uint32_t n, uint32_t nb, const Entry* ent, Bucket s
 template <int T, int BLOCK>
 __device__ void flush_stage(SieveShKeys<T, BLOCK>& sh, const SieveParams& P) {
   __syncthreads();
-  const uint32_t n = min(sh.stage_n, static_cast<uint32_t>(T));  // later slots went straight out
+  const uint32_t n = min(sh.stage_n, static_cast<uint32_t>(SieveShKeys<T, BLOCK>::kStage));  // later slots went straight out
   const uint64_t cap1 = P.cap1, W = gridDim.x;
   Entry* l1 = P.l1 + static_cast<uint64_t>(blockIdx.x) * cap1;
   const uint16_t* sb = sh.sb;
@@ -276,7 +279,7 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
       if constexpr (MODE == MODE_KEYS) {
         // Written out once less than the margin is free; stage_n is stable
         // here (after the previous barrier), so the decision is uniform.
-        if (sh.stage_n > static_cast<uint32_t>(T - T / kStageMarginDiv)) flush_stage<T, BLOCK>(sh, P);
+        if (sh.stage_n > static_cast<uint32_t>(Sh::kStage - T / kStageMarginDiv)) flush_stage<T, BLOCK>(sh, P);
       }
       const uint32_t cnt = min(static_cast<uint32_t>(T), len - base);
       const uint64_t x0 = start + base;
@@ -411,7 +414,7 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
             const Entry e = make_entry(pos43, h >> 11);
             const uint32_t bk = static_cast<uint32_t>(h) & P.b1mask;
             const uint32_t slot = sbase + k;
-            if (slot < static_cast<uint32_t>(T)) {
+            if (slot < static_cast<uint32_t>(Sh::kStage)) {
               sh.stage[slot] = e;
               sh.sb[slot] = static_cast<uint16_t>(bk);
             } else {
