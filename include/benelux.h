@@ -145,7 +145,7 @@ typedef struct {
   uint64_t integers;          /* x values whose keys were generated, per pass     */
   uint64_t entries;           /* entries written by all passes                    */
   uint64_t candidates;        /* candidate pairs emitted by the join              */
-  uint64_t pairs;             /* verified pairs (before the kinds filter)         */
+  uint64_t pairs;             /* verified pairs reported (kinds filter applied)   */
   uint32_t launches[5];       /* launches per kernel: sieve, partition, join, verify, radicals */
   double kernel_ms[5];        /* summed device time per kernel, same order        */
   double total_ms;            /* host wall time of the call                       */
@@ -165,6 +165,10 @@ int bx_get_stats(bx_ctx* ctx, bx_stats* out);
  *   "group"        first-level buckets per second-level launch (1, 2, 4, 8; 0 = 8)
  *   "tile"         sieve LDS tile: 2048 (two workgroups per CU) or 4096 (one; 0 = 4096)
  *   "graph"        1 = batched calls run as one captured HIP graph (default 1)
+ *   "fp_bits"      for tests of the verification: keep only the top 11 and
+ *                  the low fp_bits bits of the 53-bit fingerprints (v in
+ *                  [12, 53]; 0 = all), so that different sets collide and
+ *                  must be dropped by the verification
  *   "prune"        1 = only integers that can be a member of a pair enter the
  *                  join (default 1; the pair lists are the same either way:
  *                  a pair's larger member n has n and n+1 non-squarefree, and

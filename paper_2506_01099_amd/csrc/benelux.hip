@@ -108,6 +108,9 @@ struct bx_ctx {
   DevBuf l1, l2, cnt1, cnt2, cand, out, flags, spill, queries, segpref, rad, acc;
   int force_passes = 0, timing = 1, verify = 1, force_b1 = -1, force_b2 = -1, force_group = 0;
   int prune = 1;            // drop x that cannot be a pair member before the join
+  // Fingerprint bits kept: all 53 in use; tests keep the top 11 (the
+  // partition bits) and a few low ones to make different sets collide.
+  uint64_t fp_mask = (1ull << kFpBits) - 1;
   int tile = kTileDefault;
   int graph_batch = 1;      // batched calls run as one captured HIP graph
   bool capturing = false;   // no event records while a stream capture is open
@@ -634,6 +637,7 @@ int enqueue_pass(bx_ctx* c, const Job& j, uint64_t ph_lo, uint64_t ph_hi, hipStr
   SieveParams P = base_sieve_params(c, *j.s);
   P.batch = j.batch;
   P.prune = c->prune;
+  P.fp_mask = c->fp_mask;
   P.pfilter = !(ph_lo == 0 && ph_hi == (1ull << 32));
   P.ph_lo = ph_lo;
   P.ph_hi = ph_hi;
@@ -698,6 +702,7 @@ int enqueue_verify(bx_ctx* c, const Job& j, uint32_t grid, hipStream_t st) {
   V.queries = static_cast<const Query*>(c->queries.p);
   V.batch = j.batch;
   V.kinds = j.kinds;
+  V.fp_mask = c->fp_mask;
   V.out = static_cast<OutPair*>(c->out.p);
   V.out_cap = kCandCap;
   V.flags = static_cast<uint32_t*>(c->flags.p);
@@ -1107,6 +1112,11 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
     c->graph_batch = v != 0;
   } else if (n == "prune") {
     c->prune = v != 0;
+  } else if (n == "fp_bits") {
+    if (v != 0 && (v < 12 || v > static_cast<int64_t>(kFpBits)))
+      return fail(BX_EINVAL, "fp_bits must be 0 or in [12, 53]");
+    const uint64_t all = (1ull << kFpBits) - 1;
+    c->fp_mask = (v == 0 || v >= 42) ? all : (all & ~((1ull << 42) - 1)) | ((1ull << v) - 1);
   } else if (n == "group") {
     if (v != 0 && v != 1 && v != 2 && v != 4 && v != 8) return fail(BX_EINVAL, "group must be 0, 1, 2, 4 or 8");
     c->force_group = static_cast<int>(v);

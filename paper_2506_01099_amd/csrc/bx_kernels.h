@@ -56,6 +56,7 @@ struct SieveParams {
   // MODE_KEYS
   int batch;
   uint32_t prune;         // drop x that cannot be a member of any pair (may_pair)
+  uint64_t fp_mask;       // fingerprint bits kept (all 53 but in tests of the verification)
   uint32_t pfilter;       // keep x only when pass_hash(key) is in [ph_lo, ph_hi)
   uint64_t ph_lo, ph_hi;
   uint32_t b1mask;  // first-level bucket = low bits of key64
@@ -411,7 +412,7 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
             const uint64_t x = x0 + i;
             const uint64_t h = key64(klo, khi, grp);
             const uint64_t pos43 = P.batch ? ((x - qa) | (static_cast<uint64_t>(grp) << kGrpShift)) : x;
-            const Entry e = make_entry(pos43, h >> 11);
+            const Entry e = make_entry(pos43, (h >> 11) & P.fp_mask);
             const uint32_t bk = static_cast<uint32_t>(h) & P.b1mask;
             const uint32_t slot = sbase + k;
             if (slot < static_cast<uint32_t>(Sh::kStage)) {
@@ -644,6 +645,7 @@ struct VerifyParams {
   const Query* queries;
   int batch;
   uint32_t kinds;
+  uint64_t fp_mask;
   OutPair* out;
   uint32_t out_cap;
   uint32_t* flags;
@@ -714,7 +716,7 @@ __global__ __launch_bounds__(BLOCK) void k_verify(VerifyParams P) {
       const bool same = (lo_m == lo_n) && (hi_m == hi_n) && m != n;
       if (!same) {
         atomicAdd(&P.flags[kFlagFalseCand], 1u);  // equal fingerprints, different sets
-      } else if ((key64(lo_m, hi_m, P.batch ? qa_idx : 0u) >> 11) != entry_fp(cd.a)) {
+      } else if (((key64(lo_m, hi_m, P.batch ? qa_idx : 0u) >> 11) & P.fp_mask) != entry_fp(cd.a)) {
         atomicAdd(&P.flags[kFlagVerifyFail], 1u);  // the entry does not hold this set's fingerprint
       } else {
         // Kind 1 iff rad(m) = rad(n) (Algorithm 2); the third-condition bit

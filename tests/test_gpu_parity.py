@@ -148,6 +148,22 @@ def test_search_2_24_matches_oracle(ctx):
     assert st["entries"] == member_count(N)
 
 
+@pytest.mark.parametrize("N", [1 << 20, 1 << 24])
+def test_fingerprint_collisions_are_dropped(ctx, N):
+    """With 23 of the 53 fingerprint bits kept, different sets share fingerprints in
+    the join; the verification recomputes the radicals and drops every such pair."""
+    ctx.set_option("fp_bits", 12)
+    try:
+        got = ctx.search(N)
+        st = ctx.stats()
+        batch = ctx.search_batch(np.array([1, 70], dtype=np.uint64), np.array([N, 1300], dtype=np.uint64))
+    finally:
+        ctx.set_option("fp_bits", 0)
+    assert got == oracle.search(N)
+    assert st["candidates"] > st["pairs"] == len(got)
+    assert batch == [oracle.search_range(1, N), oracle.search_range(70, 1300)]
+
+
 def test_member_test_off_same_pairs(ctx):
     """Without the member test every x becomes an entry; the pairs are the same."""
     N = 1 << 22
