@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-unpruned", action="store_true",
                     help="skip the comparison run with the member test off")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the sort-join ablation run")
     ap.add_argument("--calib", action="store_true",
                     help="first copy 4 GiB with a plain copy kernel (reference for HBM counters)")
     ap.add_argument("--parse-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -274,6 +276,20 @@ def main():
         line["without_member_test"] = {"integers_per_s": N / total0, "ms_per_step": total0 * 1e3,
                                        "passes": agg0["passes"], "entries_per_step": agg0["entries"],
                                        "kernel_ms_per_step": agg0["kernel_ms"]}
+    if not args.no_ablation:
+        # The same search with the sort join per partition instead of the LDS
+        # hash join (Algorithm 2 per partition); the pair list must not change.
+        log("same search with the sort join ...")
+        bx.set_option("join", 1)
+        try:
+            p1, total1, per1, agg1 = run_plain(bx, N, 1, 1)
+        finally:
+            bx.set_option("join", 0)
+        if p1 != pairs:
+            raise SystemExit("pair lists differ between the hash join and the sort join")
+        line["sort_join_ablation"] = {"integers_per_s": N / total1, "ms_per_step": total1 * 1e3,
+                                      "join_ms": agg1["kernel_ms"]["join"],
+                                      "hash_join_ms": line["kernel_ms_per_step"]["join"]}
     if not args.no_batched or args.served > 0:
         if os.path.exists(args.tuning):
             bx.load_tuning(args.tuning)

@@ -169,6 +169,9 @@ int bx_get_stats(bx_ctx* ctx, bx_stats* out);
  *                  the low fp_bits bits of the 53-bit fingerprints (v in
  *                  [12, 53]; 0 = all), so that different sets collide and
  *                  must be dropped by the verification
+ *   "join"         0 = LDS hash join per partition (default), 1 = sort join per
+ *                  partition (Algorithm 2 on each partition, every pair of a
+ *                  run of equal keys reported; an ablation)
  *   "prune"        1 = only integers that can be a member of a pair enter the
  *                  join (default 1; the pair lists are the same either way:
  *                  a pair's larger member n has n and n+1 non-squarefree, and

@@ -108,6 +108,7 @@ struct bx_ctx {
   DevBuf l1, l2, cnt1, cnt2, cand, out, flags, spill, queries, segpref, rad, acc;
   int force_passes = 0, timing = 1, verify = 1, force_b1 = -1, force_b2 = -1, force_group = 0;
   int prune = 1;            // drop x that cannot be a pair member before the join
+  int join_sort = 0;        // 1: the sort join per partition (ablation of the hash join)
   // Fingerprint bits kept: all 53 in use; tests keep the top 11 (the
   // partition bits) and a few low ones to make different sets collide.
   uint64_t fp_mask = (1ull << kFpBits) - 1;
@@ -685,7 +686,10 @@ int enqueue_pass(bx_ctx* c, const Job& j, uint64_t ph_lo, uint64_t ph_hi, hipStr
     J.flags = d_flags;
     {
       LaunchTimer t(c, K_JOIN, st);
-      hipLaunchKernelGGL((k_join<kJoinBlock>), dim3(static_cast<uint32_t>(j.ngsub)), dim3(kJoinBlock), 0, st, J);
+      if (c->join_sort)
+        hipLaunchKernelGGL((k_join_sort<kJoinBlock>), dim3(static_cast<uint32_t>(j.ngsub)), dim3(kJoinBlock), 0, st, J);
+      else
+        hipLaunchKernelGGL((k_join<kJoinBlock>), dim3(static_cast<uint32_t>(j.ngsub)), dim3(kJoinBlock), 0, st, J);
     }
     BX_HIP(hipGetLastError());
   }
@@ -1112,6 +1116,9 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
     c->graph_batch = v != 0;
   } else if (n == "prune") {
     c->prune = v != 0;
+  } else if (n == "join") {
+    if (v != 0 && v != 1) return fail(BX_EINVAL, "join must be 0 (hash) or 1 (sort)");
+    c->join_sort = static_cast<int>(v);
   } else if (n == "fp_bits") {
     if (v != 0 && (v < 12 || v > static_cast<int64_t>(kFpBits)))
       return fail(BX_EINVAL, "fp_bits must be 0 or in [12, 53]");

@@ -636,6 +636,86 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
   }
 }
 
+// Sort join of one second-level partition, the ablation of the LDS hash join:
+// Algorithm 2 (sort, then compare neighbours) applied per partition, with every
+// pair of a run of equal keys reported rather than adjacent ones only.  The low
+// 32 bits of each fingerprint, packed with the entry's index, are bitonic-
+// sorted in LDS; runs of equal words are compared on the full fingerprint and
+// query.  A partition larger than one LDS chunk is joined chunk by chunk: every
+// later entry binary-searches each sorted chunk.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_join_sort(JoinParams P) {
+  constexpr int kIdx = 13;  // index bits (kJoinCap = 8192)
+  static_assert(kJoinCap <= (1 << kIdx), "index field");
+  __shared__ uint64_t key[kJoinCap];
+  const int tid = threadIdx.x;
+  const uint64_t sbk = blockIdx.x;
+  if (sbk >= P.n_sub) return;
+  const uint32_t n = min(P.cnt2[sbk], P.cap2);
+  __syncthreads();
+  // This workgroup is the only reader of the cursor: clear it for the next group.
+  if (tid == 0) P.cnt2[sbk] = 0;
+  if (n < 2) return;
+  const Entry* src = P.l2 + sbk * P.cap2;
+  auto same = [&](const Entry& a, const Entry& b) {
+    return entry_fp(a) == entry_fp(b) && entry_grp(a, P.gmask) == entry_grp(b, P.gmask);
+  };
+  for (uint32_t i0 = 0; i0 < n; i0 += kJoinCap) {
+    const uint32_t m = min(static_cast<uint32_t>(kJoinCap), n - i0);
+    uint32_t npad = 2;
+    while (npad < m) npad <<= 1;
+    for (uint32_t i = tid; i < npad; i += BLOCK)
+      key[i] = i < m ? (static_cast<uint64_t>(static_cast<uint32_t>(entry_fp(src[i0 + i]))) << kIdx) | i : ~0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= npad; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        for (uint32_t t = tid; t < npad / 2; t += BLOCK) {
+          const uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1)), l = i | j;
+          const uint64_t a = key[i], b = key[l];
+          if ((a > b) == ((i & k) == 0)) {
+            key[i] = b;
+            key[l] = a;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // Runs of equal 32-bit fingerprint words inside the chunk: the thread at a
+    // run's first element compares every pair of the run in full.
+    for (uint32_t i = tid; i + 1 < m; i += BLOCK) {
+      const uint64_t h = key[i] >> kIdx;
+      if ((i > 0 && (key[i - 1] >> kIdx) == h) || (key[i + 1] >> kIdx) != h) continue;
+      uint32_t end = i + 1;
+      while (end < m && (key[end] >> kIdx) == h) ++end;
+      for (uint32_t a = i; a < end; ++a) {
+        const Entry ea = src[i0 + static_cast<uint32_t>(key[a] & ((1u << kIdx) - 1))];
+        for (uint32_t b = a + 1; b < end; ++b) {
+          const Entry eb = src[i0 + static_cast<uint32_t>(key[b] & ((1u << kIdx) - 1))];
+          if (same(ea, eb)) emit_cand(P, ea, eb);
+        }
+      }
+    }
+    // Every later entry searches this sorted chunk.
+    for (uint32_t jj = i0 + m + tid; jj < n; jj += BLOCK) {
+      const Entry g = src[jj];
+      const uint64_t h = static_cast<uint32_t>(entry_fp(g));
+      uint32_t lo = 0, hi = m;  // first word with key >> kIdx >= h
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((key[mid] >> kIdx) < h)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      for (uint32_t a = lo; a < m && (key[a] >> kIdx) == h; ++a) {
+        const Entry f = src[i0 + static_cast<uint32_t>(key[a] & ((1u << kIdx) - 1))];
+        if (same(g, f)) emit_cand(P, g, f);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 struct VerifyParams {
   const Cand* cand;
   const uint32_t* n_cand;  // candidate count, read on the device (graph replays)

@@ -164,6 +164,49 @@ def test_fingerprint_collisions_are_dropped(ctx, N):
     assert batch == [oracle.search_range(1, N), oracle.search_range(70, 1300)]
 
 
+@pytest.mark.parametrize("N", [1 << 20, 1 << 24])
+def test_sort_join_matches_oracle(ctx, N):
+    """The sort-join ablation (Algorithm 2 per partition, all pairs of a run) gives the
+    same lists as the hash join and the oracle."""
+    ctx.set_option("join", 1)
+    try:
+        got = ctx.search(N)
+    finally:
+        ctx.set_option("join", 0)
+    assert got == oracle.search(N)
+
+
+def test_sort_join_chunks_collisions_and_batch(ctx):
+    """Partitions of several LDS chunks (one first- and one second-level bit), colliding
+    fingerprints and a batch, all through the sort join."""
+    from paper_2506_01099_amd.inputs import planted_queries
+
+    ctx.set_option("join", 1)
+    try:
+        ctx.set_option("b1_bits", 1)
+        ctx.set_option("b2_bits", 1)
+        try:
+            chunked = ctx.search(1 << 18)
+        finally:
+            ctx.set_option("b1_bits", 0)
+            ctx.set_option("b2_bits", 0)
+        ctx.set_option("fp_bits", 12)
+        try:
+            colliding = ctx.search(1 << 22)
+            st = ctx.stats()
+        finally:
+            ctx.set_option("fp_bits", 0)
+        a, b = planted_queries()
+        batch = ctx.search_batch(a, b)
+        full = ctx.search(1 << 28)
+    finally:
+        ctx.set_option("join", 0)
+    assert chunked == oracle.search(1 << 18)
+    assert colliding == oracle.search(1 << 22) and st["candidates"] > st["pairs"]
+    assert batch == [oracle.search_range(int(x), int(y)) for x, y in zip(a, b)]
+    assert full == theorem1_pairs(1 << 28)
+
+
 def test_member_test_off_same_pairs(ctx):
     """Without the member test every x becomes an entry; the pairs are the same."""
     N = 1 << 22
