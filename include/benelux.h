@@ -116,7 +116,9 @@ int bx_search_batch(bx_ctx* ctx, const uint64_t* a, const uint64_t* b, size_t q,
  * bx_submit never blocks when wait == 0 (BX_EBUSY if the request can never fit
  * the budget).  bx_poll reports completion, bx_take hands over the pair list
  * (malloc'd) and releases the ticket.  Times are seconds on the library's
- * monotonic clock (bx_now). */
+ * monotonic clock (bx_now).  Each of the max_inflight lanes is a context of
+ * its own that takes the owner's search options (tile, seg_len, verify,
+ * prune, join, fp_bits, group) as they are when serving starts. */
 int bx_serve_start(bx_ctx* ctx, uint64_t budget_bytes, int max_inflight);
 int bx_serve_stop(bx_ctx* ctx);
 int bx_submit(bx_ctx* ctx, uint64_t a, uint64_t b, uint32_t kinds, uint64_t* ticket);

@@ -1272,8 +1272,14 @@ int bx_serve_start(bx_ctx* c, uint64_t budget_bytes, int max_inflight) {
       for (bx_ctx* l : S->lanes) bx_destroy(l);
       return rc;
     }
+    // The lanes search as the owner is set up at the start of serving.
     lane->seg_len = c->seg_len;
     lane->tile = c->tile;
+    lane->verify = c->verify;
+    lane->prune = c->prune;
+    lane->join_sort = c->join_sort;
+    lane->fp_mask = c->fp_mask;
+    lane->force_group = c->force_group;
     lane->timing = 0;
     lane->graph_batch = 0;  // batch shapes change from batch to batch: no graph reuse
     S->lanes.push_back(lane);

@@ -419,6 +419,36 @@ def test_served_alone_equals_in_mix(ctx):
         assert td >= ts
 
 
+def test_served_kinds_and_lane_options(ctx):
+    """Requests with different kinds masks share batches; the lanes run with the owner's
+    options at serve start (here the sort join)."""
+    import time
+
+    from paper_2506_01099_amd import Server
+
+    reqs = [(1, 1 << 20, 1), (1, 1 << 20, 2), (1, 1 << 20, 4), (30, 100000, 7), (2, 9, 3)]
+    ctx.set_option("join", 1)
+    try:
+        srv = Server(ctx, budget_bytes=8 << 30, max_inflight=2)
+    finally:
+        ctx.set_option("join", 0)
+    try:
+        tickets = [srv.submit(a, b, k) for a, b, k in reqs]
+        deadline = time.time() + 60
+        results = {}
+        while len(results) < len(tickets) and time.time() < deadline:
+            for t in tickets:
+                if t not in results and srv.poll(t):
+                    results[t] = srv.take(t)[0]
+            time.sleep(0.001)
+    finally:
+        srv.stop()
+    assert len(results) == len(tickets)
+    for t, (a, b, k) in zip(tickets, reqs):
+        want = oracle.search_range(a, b, k & 3) if k & 3 else []  # no pair meets the third condition
+        assert results[t] == want, (a, b, k)
+
+
 # --- graph capture, tiles, autotuner -----------------------------------------------------
 
 def test_batch_graph_replays_match_eager(ctx):
