@@ -638,7 +638,6 @@ int enqueue_pass(bx_ctx* c, const Job& j, uint64_t ph_lo, uint64_t ph_hi, hipStr
   SieveParams P = base_sieve_params(c, *j.s);
   P.batch = j.batch;
   P.prune = c->prune;
-  P.fp_mask = c->fp_mask;
   P.pfilter = !(ph_lo == 0 && ph_hi == (1ull << 32));
   P.ph_lo = ph_lo;
   P.ph_hi = ph_hi;
@@ -667,12 +666,18 @@ int enqueue_pass(bx_ctx* c, const Job& j, uint64_t ph_lo, uint64_t ph_hi, hipStr
     Q.cap2 = plan.cap2;
     Q.cnt2 = static_cast<uint32_t*>(c->cnt2.p);
     Q.b2shift = plan.b2bits ? kFpBits - plan.b2bits : 0;
+    Q.fp_mask = c->fp_mask;
     Q.b2mask = j.B2 - 1;
     Q.gmask = j.gmask;
     Q.flags = d_flags;
     {
       LaunchTimer t(c, K_PART, st);
-      hipLaunchKernelGGL((k_partition<kPartBlock>), dim3(static_cast<uint32_t>(j.part_grid)), dim3(kPartBlock), 0, st, Q);
+      if (c->fp_mask != (1ull << kFpBits) - 1)
+        hipLaunchKernelGGL((k_partition<kPartBlock, true>), dim3(static_cast<uint32_t>(j.part_grid)), dim3(kPartBlock), 0,
+                           st, Q);
+      else
+        hipLaunchKernelGGL((k_partition<kPartBlock, false>), dim3(static_cast<uint32_t>(j.part_grid)), dim3(kPartBlock),
+                           0, st, Q);
     }
     BX_HIP(hipGetLastError());
     JoinParams J;

@@ -56,7 +56,6 @@ struct SieveParams {
   // MODE_KEYS
   int batch;
   uint32_t prune;         // drop x that cannot be a member of any pair (may_pair)
-  uint64_t fp_mask;       // fingerprint bits kept (all 53 but in tests of the verification)
   uint32_t pfilter;       // keep x only when pass_hash(key) is in [ph_lo, ph_hi)
   uint64_t ph_lo, ph_hi;
   uint32_t b1mask;  // first-level bucket = low bits of key64
@@ -412,7 +411,7 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
             const uint64_t x = x0 + i;
             const uint64_t h = key64(klo, khi, grp);
             const uint64_t pos43 = P.batch ? ((x - qa) | (static_cast<uint64_t>(grp) << kGrpShift)) : x;
-            const Entry e = make_entry(pos43, (h >> 11) & P.fp_mask);
+            const Entry e = make_entry(pos43, h >> 11);
             const uint32_t bk = static_cast<uint32_t>(h) & P.b1mask;
             const uint32_t slot = sbase + k;
             if (slot < static_cast<uint32_t>(Sh::kStage)) {
@@ -450,6 +449,7 @@ struct PartParams {
   uint32_t cap2;
   uint32_t* cnt2;  // G x B2 cursors (zero on entry)
   uint32_t b2shift, b2mask;  // second-level partition = top bits of the fingerprint
+  uint64_t fp_mask;          // fingerprint bits kept (all 53 but in tests of the verification)
   uint32_t gmask;
   uint32_t* flags;
 };
@@ -461,7 +461,7 @@ struct PartParams {
 // before they are written back.  The bucket's chunks are split into nbw
 // contiguous ranges, one per workgroup; the next chunk is loaded into
 // registers while the current one is scattered.
-template <int BLOCK>
+template <int BLOCK, bool MASK_FP>
 __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
   constexpr int EPT = kPartChunk / BLOCK;
   static_assert(kPartChunk % BLOCK == 0, "chunk shape");
@@ -507,7 +507,12 @@ __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
     for (int q = 0; q < EPT; ++q) {
       const uint32_t i = tid + q * BLOCK;
       if (i < n) {
-        ent[i] = e[q];
+        Entry x = e[q];
+        if constexpr (MASK_FP) {  // tests of the verification only
+          const uint64_t pos43 = entry_pos43(x);
+          x = make_entry(pos43, entry_fp(x) & P.fp_mask);
+        }
+        ent[i] = x;
         sbk[i] = static_cast<uint16_t>(static_cast<uint32_t>(entry_fp(e[q]) >> P.b2shift) & P.b2mask);
       }
     }
@@ -593,26 +598,40 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
     }
     for (uint32_t s = tid; s < slots; s += BLOCK) table[s] = kEmpty;
     __syncthreads();
+    // Every entry first tries to claim its home slot; the EPT claims of a
+    // thread are independent and issued together (at load <= 0.5 most
+    // succeed).  A claim that finds the slot taken compares the tag and walks
+    // on, claiming each next slot, until one is empty.
+    // (In groups of four, to stay within the registers of 32 waves per CU.)
+    constexpr int kClaim = EPT < 4 ? EPT : 4;
+    static_assert(EPT % kClaim == 0, "claim groups");
 #pragma unroll
-    for (int k = 0; k < EPT; ++k) {
-      const uint32_t i = tid + k * BLOCK;
-      if (i >= m) continue;
-      const uint64_t fk = entry_fp(e[k]);
-      const uint32_t gk = entry_grp(e[k], P.gmask);
-      const uint32_t h = static_cast<uint32_t>(fk);
-      const uint32_t mine = (h & ~kIdxMask) | i;
-      uint32_t s = h & smask;
-      for (;;) {
-        uint32_t v = table[s];
-        if (v == kEmpty) {
+    for (int k0 = 0; k0 < EPT; k0 += kClaim) {
+      uint32_t got[kClaim];
+#pragma unroll
+      for (int u = 0; u < kClaim; ++u) {
+        const uint32_t i = tid + (k0 + u) * BLOCK;
+        const uint32_t h = static_cast<uint32_t>(entry_fp(e[k0 + u]));
+        got[u] = i < m ? atomicCAS(&table[h & smask], kEmpty, (h & ~kIdxMask) | i) : kEmpty;
+      }
+#pragma unroll
+      for (int u = 0; u < kClaim; ++u) {
+        if (got[u] == kEmpty) continue;  // claimed (or no entry)
+        const int k = k0 + u;
+        const uint64_t fk = entry_fp(e[k]);
+        const uint32_t gk = entry_grp(e[k], P.gmask);
+        const uint32_t h = static_cast<uint32_t>(fk);
+        const uint32_t mine = (h & ~kIdxMask) | (tid + k * BLOCK);
+        uint32_t v = got[u], s = h & smask;
+        for (;;) {
+          if (((v ^ mine) & ~kIdxMask) == 0) {
+            const Entry f = src[i0 + (v & kIdxMask)];
+            if (entry_fp(f) == fk && entry_grp(f, P.gmask) == gk) emit_cand(P, e[k], f);
+          }
+          s = (s + 1) & smask;
           v = atomicCAS(&table[s], kEmpty, mine);
           if (v == kEmpty) break;
         }
-        if (((v ^ mine) & ~kIdxMask) == 0) {
-          const Entry f = src[i0 + (v & kIdxMask)];
-          if (entry_fp(f) == fk && entry_grp(f, P.gmask) == gk) emit_cand(P, e[k], f);
-        }
-        s = (s + 1) & smask;
       }
     }
     __syncthreads();
