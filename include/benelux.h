@@ -117,8 +117,8 @@ int bx_search_batch(bx_ctx* ctx, const uint64_t* a, const uint64_t* b, size_t q,
  * the budget).  bx_poll reports completion, bx_take hands over the pair list
  * (malloc'd) and releases the ticket.  Times are seconds on the library's
  * monotonic clock (bx_now).  Each of the max_inflight lanes is a context of
- * its own that takes the owner's search options (tile, seg_len, verify,
- * prune, join, fp_bits, group) as they are when serving starts. */
+ * its own that takes the owner's search options (tile, seg_len, prune,
+ * join, fp_bits, group) as they are when serving starts. */
 int bx_serve_start(bx_ctx* ctx, uint64_t budget_bytes, int max_inflight);
 int bx_serve_stop(bx_ctx* ctx);
 int bx_submit(bx_ctx* ctx, uint64_t a, uint64_t b, uint32_t kinds, uint64_t* ticket);
@@ -161,7 +161,6 @@ int bx_get_stats(bx_ctx* ctx, bx_stats* out);
  *   "passes"       force the number of hash passes (any count, 0 = plan)
  *   "seg_len"      sieve segment length (multiple of the tile, 0 = default)
  *   "timing"       1 = record HIP events per kernel (default 1)
- *   "verify"       1 = recompute every candidate by trial division (default 1)
  *   "b1_bits"      force the first partition fan-out (0 = plan)
  *   "b2_bits"      force the second partition fan-out, <= 11 (0 = plan)
  *   "group"        first-level buckets per second-level launch (1, 2, 4, 8; 0 = 8)

@@ -106,7 +106,7 @@ struct bx_ctx {
   PrimePow* d_pp = nullptr;
   DenseTab* d_dense[2] = {nullptr, nullptr};
   DevBuf l1, l2, cnt1, cnt2, cand, out, flags, spill, queries, segpref, rad, acc;
-  int force_passes = 0, timing = 1, verify = 1, force_b1 = -1, force_b2 = -1, force_group = 0;
+  int force_passes = 0, timing = 1, force_b1 = -1, force_b2 = -1, force_group = 0;
   int prune = 1;            // drop x that cannot be a pair member before the join
   int join_sort = 0;        // 1: the sort join per partition (ablation of the hash join)
   // Fingerprint bits kept: all 53 in use; tests keep the top 11 (the
@@ -809,11 +809,15 @@ int run_passes_graph(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* re
   *redo = 0;
   // Every launch shape and every buffer address the graph's kernels use.
   char key[1024];
-  std::snprintf(key, sizeof(key), "%u %llu %u %u %u %u %llu %u %d %u %d %u %p %p %p %p %p %p %p %p %p %p %p %p %p",
+  // Every launch shape, every option baked into a kernel argument or choice,
+  // and every buffer address the graph's kernels use.
+  std::snprintf(key, sizeof(key),
+                "%u %llu %u %u %u %u %llu %u %d %u %d %u %d %d %llx %p %p %p %p %p %p %p %p %p %p %p %p %p",
                 j.plan.passes, static_cast<unsigned long long>(j.plan.cap1), j.plan.cap2, j.plan.b1bits, j.plan.b2bits,
                 j.G, static_cast<unsigned long long>(j.s->n_segs), static_cast<uint32_t>(j.s->q.size()), j.batch,
-                j.kinds, c->tile, c->seg_len, c->l1.p, c->l2.p, c->spill.p, c->cnt1.p, c->cnt2.p, c->cand.p, c->out.p,
-                c->flags.p, c->acc.p, c->queries.p, c->segpref.p, static_cast<void*>(c->d_pp),
+                j.kinds, c->tile, c->seg_len, c->prune, c->join_sort,
+                static_cast<unsigned long long>(c->fp_mask), c->l1.p, c->l2.p, c->spill.p, c->cnt1.p, c->cnt2.p,
+                c->cand.p, c->out.p, c->flags.p, c->acc.p, c->queries.p, c->segpref.p, static_cast<void*>(c->d_pp),
                 static_cast<void*>(c->d_primes));
   if (!c->graph_exec || c->graph_key != key) {
     if (c->graph_exec) {
@@ -1112,8 +1116,6 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
     c->seg_len = static_cast<uint32_t>(v);
   } else if (n == "timing") {
     c->timing = v != 0;
-  } else if (n == "verify") {
-    c->verify = v != 0;
   } else if (n == "tile") {
     if (v != 0 && v != kTileSmall && v != kTileLarge) return fail(BX_EINVAL, "tile must be 0, 2048 or 4096");
     c->tile = v == 0 ? kTileDefault : static_cast<int>(v);
@@ -1280,7 +1282,6 @@ int bx_serve_start(bx_ctx* c, uint64_t budget_bytes, int max_inflight) {
     // The lanes search as the owner is set up at the start of serving.
     lane->seg_len = c->seg_len;
     lane->tile = c->tile;
-    lane->verify = c->verify;
     lane->prune = c->prune;
     lane->join_sort = c->join_sort;
     lane->fp_mask = c->fp_mask;

@@ -451,6 +451,24 @@ def test_served_kinds_and_lane_options(ctx):
 
 # --- graph capture, tiles, autotuner -----------------------------------------------------
 
+def test_batch_graph_follows_options(ctx):
+    """The cached batch graph is captured again when an option it bakes in changes."""
+    from paper_2506_01099_amd.inputs import planted_queries
+
+    a, b = planted_queries()
+    want = [oracle.search_range(int(x), int(y)) for x, y in zip(a, b)]
+    assert ctx.search_batch(a, b) == want
+    for name, val, default in (("join", 1, 0), ("prune", 0, 1), ("fp_bits", 12, 0)):
+        ctx.set_option(name, val)
+        try:
+            got = ctx.search_batch(a, b)
+            again = ctx.search_batch(a, b)
+        finally:
+            ctx.set_option(name, default)
+        assert got == again == want, name
+    assert ctx.search_batch(a, b) == want
+
+
 def test_batch_graph_replays_match_eager(ctx):
     """The captured batch graph, replayed with eager work and syncs in between, equals the eager path."""
     import torch
