@@ -128,7 +128,7 @@ def parse_counters(fetch_dir, write_dir):
     w_scale = CALIB_BYTES / (w_copy * 1024) if w_copy else None
     out = {"source_hash": kernel_source_hash(), "calib_bytes": CALIB_BYTES,
            "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
-    for k, key in (("sieve", "k_sieve"), ("partition", "k_partition"), ("join", "k_join")):
+    for k, key in (("sieve", "k_sieve<"), ("partition", "k_partition<"), ("join", "k_join<")):
         f, w = pick(fetch, key), pick(write, key)
         if f is None or w is None or not f_scale or not w_scale:
             continue
