@@ -124,6 +124,13 @@ __device__ __forceinline__ uint64_t strip_two(uint64_t x) {
   return tz >= 2 ? (x >> (tz - 1)) : x;
 }
 
+// strip_two for x whose low 32-bit word is not zero (then ctz(x) is the
+// count of the low word alone).
+__device__ __forceinline__ uint64_t strip_two_lo(uint64_t x) {
+  const uint32_t tz = static_cast<uint32_t>(__builtin_ctz(static_cast<uint32_t>(x)));
+  return x >> (max(tz, 1u) - 1u);
+}
+
 // u * v <= b for u, v, b < 2^43, without overflow.
 __device__ __forceinline__ bool prod_le(uint64_t u, uint64_t v, uint64_t b) {
   return __umul64hi(u, v) == 0 && u * v <= b;

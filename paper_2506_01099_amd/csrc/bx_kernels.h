@@ -81,7 +81,7 @@ struct SieveShKeys : SieveShCommon<T, BLOCK> {
   // 12 B entries leave room), one tile with the 2048 tile (two per CU).
   static constexpr int kStage = T >= 4096 ? T + T / 2 : T;
   Entry stage[kStage];
-  uint16_t sb[kStage], perm[kStage];  // perm also holds the waves' kept lists (T entries)
+  uint16_t sb[kStage], perm[kStage];
   uint32_t cnt[kB1Max], gofs[kB1Max], lcur[kB1Max];
 };
 
@@ -153,6 +153,45 @@ __device__ void scatter_runs(uint32_t n, uint32_t nb, const Entry* ent, Bucket s
   __syncthreads();
 }
 
+// A kept integer waits in its stage slot as (rad(x), rad(x + 1), i), i = x - x0
+// its index in the tile, until the next tile's division phase (or a flush)
+// turns it into an entry with every thread of the workgroup at work.  Values
+// are below 2^42 and i below 2^12, so the three fit the slot's 96 bits.
+__device__ __forceinline__ Entry pack_pending(uint64_t a, uint64_t b, uint32_t i) {
+  Entry e;
+  e.w0 = static_cast<uint32_t>(a);
+  e.w1 = static_cast<uint32_t>(a >> 32) | (static_cast<uint32_t>(b) << 10);
+  e.w2 = static_cast<uint32_t>(b >> 22) | (i << 20);
+  return e;
+}
+
+// Entry of the kept integer x = x0 + i with rad(x) = a and rad(x + 1) = b;
+// *bucket receives its first-level bucket.
+__device__ __forceinline__ Entry kept_entry(const SieveParams& P, uint64_t a, uint64_t b, uint64_t x, uint64_t qa,
+                                            uint32_t grp, uint32_t* bucket) {
+  const uint64_t klo = a < b ? a : b, khi = a < b ? b : a;
+  const uint64_t h = key64(klo, khi, grp);
+  const uint64_t pos43 = P.batch ? ((x - qa) | (static_cast<uint64_t>(grp) << kGrpShift)) : x;
+  *bucket = static_cast<uint32_t>(h) & P.b1mask;
+  return make_entry(pos43, h >> 11);
+}
+
+// Turns the waiting slots [lo, hi) of one tile (first value x0, query start
+// qa, query id grp) into entries and their buckets, one slot per thread.
+template <int T, int BLOCK>
+__device__ void build_pending(SieveShKeys<T, BLOCK>& sh, const SieveParams& P, uint32_t lo, uint32_t hi, uint64_t x0,
+                              uint64_t qa, uint32_t grp) {
+  for (uint32_t s = lo + threadIdx.x; s < hi; s += BLOCK) {
+    const Entry r = sh.stage[s];
+    const uint64_t a = r.w0 | (static_cast<uint64_t>(r.w1 & 0x3FFu) << 32);
+    const uint64_t b = (r.w1 >> 10) | (static_cast<uint64_t>(r.w2 & 0xFFFFFu) << 22);
+    const uint32_t i = r.w2 >> 20;
+    uint32_t bk;
+    sh.stage[s] = kept_entry(P, a, b, x0 + i, qa, grp, &bk);
+    sh.sb[s] = static_cast<uint16_t>(bk);
+  }
+}
+
 template <int T, int BLOCK>
 __device__ void flush_stage(SieveShKeys<T, BLOCK>& sh, const SieveParams& P) {
   __syncthreads();
@@ -214,6 +253,11 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
   __syncthreads();
   uint64_t* spill = P.spill + static_cast<uint64_t>(blockIdx.x) * P.spill_cap;
 
+  // The previous tile's kept integers wait in stage slots [plo, ...); that
+  // tile started at px0 in the query starting at pqa with id pgrp.
+  uint32_t plo = 0;
+  uint64_t px0 = 0, pqa = 0;
+  uint32_t pgrp = 0;
   for (uint64_t s = blockIdx.x; s < P.n_segs; s += gridDim.x) {
     // Segment s -> query q and its x-interval [start, start + len).
     uint32_t lo = 0, hi = P.n_queries;
@@ -276,18 +320,34 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
     const uint32_t nh = min(sh.hit_n, kHitCap + P.spill_cap);
 
     for (uint32_t base = 0; base < len; base += T) {
+      // Waiting slots [plo, phi) are built in this tile's division phase.
+      uint32_t phi = 0;
       if constexpr (MODE == MODE_KEYS) {
         // Written out once less than the margin is free; stage_n is stable
         // here (after the previous barrier), so the decision is uniform.
-        if (sh.stage_n > static_cast<uint32_t>(Sh::kStage - T / kStageMarginDiv)) flush_stage<T, BLOCK>(sh, P);
+        const uint32_t sn = __builtin_amdgcn_readfirstlane(sh.stage_n);
+        phi = sn;
+        if (sn > static_cast<uint32_t>(Sh::kStage - T / kStageMarginDiv)) {
+          build_pending<T, BLOCK>(sh, P, plo, min(sn, static_cast<uint32_t>(Sh::kStage)), px0, pqa, pgrp);
+          flush_stage<T, BLOCK>(sh, P);
+          plo = phi = 0;
+        }
       }
       const uint32_t cnt = min(static_cast<uint32_t>(T), len - base);
       const uint64_t x0 = start + base;
       // r[n] <- n with the prime 2 already reduced (count trailing zeros).
       // The whole tile is written (values past cnt are never used).
+      // Uniform: no x of the tile (x0 .. x0 + T) has a zero low word.
+      const uint32_t x0lo = static_cast<uint32_t>(x0);
+      if (x0lo != 0u && x0lo <= 0xFFFFFFFFu - static_cast<uint32_t>(T)) {
 #pragma unroll
-      for (int it = 0; it < ITER; ++it) sh.tile[it * BLOCK + tid] = strip_two(x0 + it * BLOCK + tid);
-      if (tid == 0) sh.tile[T] = strip_two(x0 + T);
+        for (int it = 0; it < ITER; ++it) sh.tile[it * BLOCK + tid] = strip_two_lo(x0 + it * BLOCK + tid);
+        if (tid == 0) sh.tile[T] = strip_two_lo(x0 + T);
+      } else {
+#pragma unroll
+        for (int it = 0; it < ITER; ++it) sh.tile[it * BLOCK + tid] = strip_two(x0 + it * BLOCK + tid);
+        if (tid == 0) sh.tile[T] = strip_two(x0 + T);
+      }
       // dres[d] = x0 mod q_d, advanced by T mod q_d from tile to tile.
       if (static_cast<uint32_t>(tid) < nd) {
         const uint32_t qd = sh.dq[tid];
@@ -325,6 +385,9 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
           lds_div(&sh.tile[pos - base], p, inv32(p));
         }
       }
+      // The previous tile's kept integers become entries while the divisions
+      // wait on LDS (they touch only stage slots).
+      if constexpr (MODE == MODE_KEYS) build_pending<T, BLOCK>(sh, P, plo, phi, px0, pqa, pgrp);
       __syncthreads();
 
       if constexpr (MODE == MODE_RAD) {
@@ -347,92 +410,91 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
           ra[it] = sh.tile[i];
           rb[it] = sh.tile[i + 1];
         }
-        bool keep[ITER];
+        // Lane masks of the wave (all 64 lanes are active here): bit l of
+        // mask[it] says whether lane l keeps its it-th integer.
         uint64_t mask[ITER];
         uint32_t total = 0;
+        const bool full = cnt == static_cast<uint32_t>(T);
 #pragma unroll
         for (int it = 0; it < ITER; ++it) {
           const uint32_t i = it * BLOCK + tid;
           const uint64_t r0 = ra[it], r1 = rb[it];
           const uint64_t x = x0 + i;
-          bool k = true;
+          uint64_t km = ~0ull;
           if (P.prune) {
             const bool s0 = r0 == x, s1 = r1 == x + 1;  // x, x + 1 squarefree
-            k = !s0 && !s1;
+            km = ~(__ballot(s0) | __ballot(s1));
             if (!upper) {
               // may_pair: a squarefree y of {x, x + 1} needs y * M <= b with
               // M = max(2, rad(other) - 1).  M > lim_hi fails for the whole
               // segment, which settles almost every such y at once; the rest
               // (M <= lim_hi, i.e. rad(other) <= lim_hi + 1) are taken exactly.
               const bool c0 = s0 && r1 <= lim_hi + 1, c1 = s1 && r0 <= lim_hi + 1;
-              if (__ballot(c0 || c1)) {
+              const uint64_t cm = __ballot(c0 || c1);
+              if (cm) {
+                bool k = false;
                 if (c0 || c1) {
                   const uint64_t M0 = r1 >= 3 ? r1 - 1 : 2, M1 = r0 >= 3 ? r0 - 1 : 2;
                   const bool p0 = !s0 || (c0 && (M0 <= lim_lo || prod_le(x, M0, qb)));
                   const bool p1 = !s1 || (c1 && (M1 <= lim_lo || prod_le(x + 1, M1, qb)));
                   k = p0 && p1;
                 }
+                km = (km & ~cm) | __ballot(k);
               }
-              if (x0 <= 3) k = k || x <= 3;
+              if (x0 <= 3) km |= __ballot(x <= 3);
             }
           }
           if (P.pfilter) {
             const uint64_t ph = pass_hash(r0 < r1 ? r0 : r1, r0 < r1 ? r1 : r0, grp);
-            k = k && ph >= P.ph_lo && ph < P.ph_hi;
+            km &= __ballot(ph >= P.ph_lo && ph < P.ph_hi);
           }
-          keep[it] = k && i < cnt;
-          mask[it] = __ballot(keep[it]);
-          total += __popcll(mask[it]);
+          if (!full) km &= __ballot(i < cnt);
+          mask[it] = km;
+          total += __popcll(km);
         }
-        // 2. Wave-local compaction: ballots rank the wave's kept integers in
-        // the wave's slice of the flush's permutation array (free outside a
-        // flush), and lane 0 reserves their stage slots with one LDS atomic.
+        // 2. Wave-local compaction: ballots rank the wave's kept integers,
+        // lane 0 reserves their stage slots with one LDS atomic, and each
+        // lane parks its kept integers' radicals in their slots.  Slots past
+        // the stage (a tile that keeps more than the margin left free) are
+        // built at once and go straight to the workgroup's regions.
         if (total) {  // uniform over the wave
-          const uint32_t lane = lane_id();
-          const uint64_t below = (1ull << lane) - 1ull;
-          uint16_t* wl = sh.perm + (tid >> 6) * (ITER * 64);
-          uint32_t wb = 0;
+          const uint64_t below = (1ull << lane_id()) - 1ull;
+          uint32_t sbase = 0;
+          if (lane_id() == 0) sbase = atomicAdd(&sh.stage_n, total);
+          sbase = __builtin_amdgcn_readfirstlane(sbase);
 #pragma unroll
           for (int it = 0; it < ITER; ++it) {
-            if (keep[it]) wl[wb + __popcll(mask[it] & below)] = static_cast<uint16_t>(it * BLOCK + tid);
-            wb += __popcll(mask[it]);
-          }
-          uint32_t sbase = 0;
-          if (lane == 0) sbase = atomicAdd(&sh.stage_n, total);
-          sbase = __builtin_amdgcn_readfirstlane(sbase);
-          __builtin_amdgcn_wave_barrier();  // LDS runs one wave's accesses in order
-          // 3. Entries of the kept integers, densely over the wave's lanes.
-          // Slots past the stage (a tile that keeps more than the margin left
-          // free) go straight to the workgroup's regions.
-          for (uint32_t k = lane; k < total; k += 64) {
-            const uint32_t i = wl[k];
-            const uint64_t a = sh.tile[i], b = sh.tile[i + 1];
-            const uint64_t klo = a < b ? a : b, khi = a < b ? b : a;
-            const uint64_t x = x0 + i;
-            const uint64_t h = key64(klo, khi, grp);
-            const uint64_t pos43 = P.batch ? ((x - qa) | (static_cast<uint64_t>(grp) << kGrpShift)) : x;
-            const Entry e = make_entry(pos43, h >> 11);
-            const uint32_t bk = static_cast<uint32_t>(h) & P.b1mask;
-            const uint32_t slot = sbase + k;
-            if (slot < static_cast<uint32_t>(Sh::kStage)) {
-              sh.stage[slot] = e;
-              sh.sb[slot] = static_cast<uint16_t>(bk);
-            } else {
-              const uint32_t g = atomicAdd(&sh.lcur[bk], 1u);
-              if (g < P.cap1)
-                P.l1[(static_cast<uint64_t>(bk) * gridDim.x + blockIdx.x) * P.cap1 + g] = e;
-              else
-                atomicOr(&P.flags[kFlagL1Overflow], 1u);
+            if ((mask[it] >> lane_id()) & 1ull) {
+              const uint32_t i = it * BLOCK + tid;
+              const uint32_t slot = sbase + __popcll(mask[it] & below);
+              if (slot < static_cast<uint32_t>(Sh::kStage)) {
+                sh.stage[slot] = pack_pending(ra[it], rb[it], i);
+              } else {
+                uint32_t bk;
+                const Entry e = kept_entry(P, ra[it], rb[it], x0 + i, qa, grp, &bk);
+                const uint32_t g = atomicAdd(&sh.lcur[bk], 1u);
+                if (g < P.cap1)
+                  P.l1[(static_cast<uint64_t>(bk) * gridDim.x + blockIdx.x) * P.cap1 + g] = e;
+                else
+                  atomicOr(&P.flags[kFlagL1Overflow], 1u);
+              }
             }
+            sbase += __popcll(mask[it]);
           }
         }
+        plo = phi;  // this tile's slots start where the stage stood at its start
+        px0 = x0;
+        pqa = qa;
+        pgrp = grp;
       }
       __syncthreads();
     }
   }
   if constexpr (MODE == MODE_KEYS) {
     __syncthreads();
-    if (sh.stage_n > 0) flush_stage<T, BLOCK>(sh, P);
+    const uint32_t sn = __builtin_amdgcn_readfirstlane(sh.stage_n);
+    build_pending<T, BLOCK>(sh, P, plo, min(sn, static_cast<uint32_t>(Sh::kStage)), px0, pqa, pgrp);
+    if (sn > 0) flush_stage<T, BLOCK>(sh, P);
     for (uint32_t b = tid; b <= P.b1mask; b += BLOCK) P.cnt1[static_cast<uint64_t>(b) * gridDim.x + blockIdx.x] = sh.lcur[b];
   }
 }
