@@ -128,7 +128,7 @@ double bx_now(void);
 
 /* Autotuner.  Times the batched search of the queries [a[i], b[i]) (q >= 1;
  * one query [1, N+1) stands for a plain search) under every combination of
- * sieve tile {2048, 4096}, segment length {2^15 .. 2^19} and second-level group
+ * sieve tile {2048, 8192}, segment length {2^15 .. 2^19} and second-level group
  * {2, 4, 8}, `reps` timed runs each after one warm-up, keeps the fastest,
  * applies it to ctx and, when path is not NULL, writes it as a one-line JSON
  * object (arch, tile, seg_len, group, ms).  Results of every run are checked
@@ -164,7 +164,7 @@ int bx_get_stats(bx_ctx* ctx, bx_stats* out);
  *   "b1_bits"      force the first partition fan-out (0 = plan)
  *   "b2_bits"      force the second partition fan-out, <= 11 (0 = plan)
  *   "group"        first-level buckets per second-level launch (1, 2, 4, 8; 0 = 8)
- *   "tile"         sieve LDS tile: 2048 (two workgroups per CU) or 4096 (one; 0 = 4096)
+ *   "tile"         sieve LDS tile: 2048 (two workgroups per CU) or 8192 (one; 0 = 8192)
  *   "graph"        1 = batched calls run as one captured HIP graph (default 1)
  *   "fp_bits"      for tests of the verification: keep only the top 11 and
  *                  the low fp_bits bits of the 53-bit fingerprints (v in

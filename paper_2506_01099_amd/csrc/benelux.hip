@@ -41,8 +41,9 @@ int fail(int code, const std::string& msg) {
   } while (0)
 
 // Two sieve shapes: LDS tiles of 2048 values with 512 threads (under 80 KB of
-// LDS, two workgroups per CU) or 4096 values with 1024 threads (one per CU).
-constexpr int kTileSmall = 2048, kTileLarge = 4096;
+// LDS, two workgroups per CU) or 8192 values with 1024 threads (one per CU;
+// eight values per thread between barriers, the faster shape).
+constexpr int kTileSmall = 2048, kTileLarge = 8192;
 constexpr int kTileDefault = kTileLarge;  // one 1024-thread workgroup per CU
 constexpr int kVerifyGrid = 2048;
 constexpr int kPartBlock = 1024;
@@ -264,7 +265,8 @@ int build_tables(bx_ctx* c) {
       if (nd >= static_cast<uint32_t>(kDenseMax)) return fail(BX_EINTERNAL, "dense prime-power table overflow");
       const uint32_t q = static_cast<uint32_t>(w.q);
       const uint32_t ub = T / q + 1;  // multiples of q among T + 1 consecutive values
-      if (slots + ub > static_cast<uint32_t>(kDenseSlotMax)) return fail(BX_EINTERNAL, "dense slot table overflow");
+      if (slots + ub > static_cast<uint32_t>(dense_slot_cap(static_cast<int>(T))))
+        return fail(BX_EINTERNAL, "dense slot table overflow");
       dt.q[nd] = q;
       dt.p[nd] = w.p;
       dt.pinv[nd] = w.pinv;
@@ -1112,12 +1114,12 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
   } else if (n == "seg_len") {
     if (v == 0) v = kDefaultSegLen;
     if (v < kTileLarge || v % kTileLarge || v > (1 << 24))
-      return fail(BX_EINVAL, "seg_len must be a multiple of 4096 in [4096, 2^24]");
+      return fail(BX_EINVAL, "seg_len must be a multiple of 8192 in [8192, 2^24]");
     c->seg_len = static_cast<uint32_t>(v);
   } else if (n == "timing") {
     c->timing = v != 0;
   } else if (n == "tile") {
-    if (v != 0 && v != kTileSmall && v != kTileLarge) return fail(BX_EINVAL, "tile must be 0, 2048 or 4096");
+    if (v != 0 && v != kTileSmall && v != kTileLarge) return fail(BX_EINVAL, "tile must be 0, 2048 or 8192");
     c->tile = v == 0 ? kTileDefault : static_cast<int>(v);
   } else if (n == "graph") {
     c->graph_batch = v != 0;

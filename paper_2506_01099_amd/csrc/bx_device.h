@@ -51,7 +51,10 @@ struct OutPair {
 // spreads their multiples over the threads of a workgroup: slot t belongs to
 // power slot_d[t] and is its (t - prefix[d])-th multiple in the tile.
 constexpr int kDenseMax = 64;
-constexpr int kDenseSlotMax = 1152;
+constexpr int kDenseSlotMax = 2304;
+// Slots a tile of T values needs at most (the odd prime powers q <= T with
+// their floor(T/q) + 1 multiples: 555 for T = 2048, 2236 for T = 8192).
+constexpr int dense_slot_cap(int T) { return T >= 8192 ? kDenseSlotMax : 576; }
 struct DenseTab {
   uint32_t n, nslots;
   uint32_t q[kDenseMax], p[kDenseMax], pinv[kDenseMax], prefix[kDenseMax];

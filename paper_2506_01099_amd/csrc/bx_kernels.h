@@ -25,14 +25,13 @@ constexpr int MODE_RAD = 0;
 constexpr int MODE_KEYS = 1;
 
 // Sparse-hit list held in LDS per segment: 1024 entries with the 2048 tile
-// (two workgroups per CU), 2048 with the 4096 tile.
+// (two workgroups per CU), 2048 with the 8192 tile.
 template <int T>
 constexpr int hit_cap() { return T >= 4096 ? 2048 : 1024; }
 constexpr int kB1Max = 1024;       // first partition fan-out
 constexpr int kB2Max = 2048;       // second partition fan-out
 constexpr int kPartChunk = 4096;   // entries per workgroup in k_partition
 constexpr uint32_t kKindThird = 4; // kinds bit: also test rad(m + 2) = rad(n + 2)
-constexpr int kStageMarginDiv = 4; // the stage is written out once less than T/4 slots are free
 constexpr int kJoinCap = 8192;     // entries of one LDS join chunk (held in registers)
 constexpr int kJoinSlots = 16384;  // LDS hash-table slots (load <= 0.5)
 constexpr int kJoinIdxBits = 14;   // slot = tag (18 bits) << 14 | entry index
@@ -74,12 +73,16 @@ struct SieveShCommon {
 };
 
 // The stage collects the kept entries of several tiles; it is written out when
-// less than T / kStageMarginDiv slots are free at the start of a tile.
+// less than kMargin slots are free at the start of a tile.
 template <int T, int BLOCK>
 struct SieveShKeys : SieveShCommon<T, BLOCK> {
-  // Stage capacity: 1.5 tiles with the 4096 tile (one workgroup per CU, the
-  // 12 B entries leave room), one tile with the 2048 tile (two per CU).
-  static constexpr int kStage = T >= 4096 ? T + T / 2 : T;
+  // Stage capacity: 4096 entries with the 8192 tile (one workgroup per CU:
+  // what the LDS leaves beside the 64 KB tile), one tile with the 2048 tile
+  // (two per CU).  The margin holds what a tile keeps in the bulk of a range
+  // (0.107 T on average, below 0.125 T); a tile that keeps more sends the
+  // excess straight to HBM.
+  static constexpr int kStage = T >= 8192 ? 4096 : T;
+  static constexpr int kMargin = T >= 8192 ? 1152 : T / 4;
   Entry stage[kStage];
   uint16_t sb[kStage], perm[kStage];
   uint32_t cnt[kB1Max], gofs[kB1Max], lcur[kB1Max];
@@ -153,15 +156,15 @@ __device__ void scatter_runs(uint32_t n, uint32_t nb, const Entry* ent, Bucket s
   __syncthreads();
 }
 
-// A kept integer waits in its stage slot as (rad(x), rad(x + 1), i), i = x - x0
-// its index in the tile, until the next tile's division phase (or a flush)
-// turns it into an entry with every thread of the workgroup at work.  Values
-// are below 2^42 and i below 2^12, so the three fit the slot's 96 bits.
-__device__ __forceinline__ Entry pack_pending(uint64_t a, uint64_t b, uint32_t i) {
+// A kept integer waits in its stage slot as (rad(x), rad(x + 1)), both below
+// 2^42 and so within the slot's 96 bits, with i = x - x0, its index in the
+// tile, in the slot's bucket word; the next tile's division phase (or a flush)
+// turns it into an entry with every thread of the workgroup at work.
+__device__ __forceinline__ Entry pack_pending(uint64_t a, uint64_t b) {
   Entry e;
   e.w0 = static_cast<uint32_t>(a);
   e.w1 = static_cast<uint32_t>(a >> 32) | (static_cast<uint32_t>(b) << 10);
-  e.w2 = static_cast<uint32_t>(b >> 22) | (i << 20);
+  e.w2 = static_cast<uint32_t>(b >> 22);
   return e;
 }
 
@@ -184,8 +187,8 @@ __device__ void build_pending(SieveShKeys<T, BLOCK>& sh, const SieveParams& P, u
   for (uint32_t s = lo + threadIdx.x; s < hi; s += BLOCK) {
     const Entry r = sh.stage[s];
     const uint64_t a = r.w0 | (static_cast<uint64_t>(r.w1 & 0x3FFu) << 32);
-    const uint64_t b = (r.w1 >> 10) | (static_cast<uint64_t>(r.w2 & 0xFFFFFu) << 22);
-    const uint32_t i = r.w2 >> 20;
+    const uint64_t b = (r.w1 >> 10) | (static_cast<uint64_t>(r.w2) << 22);
+    const uint32_t i = sh.sb[s];
     uint32_t bk;
     sh.stage[s] = kept_entry(P, a, b, x0 + i, qa, grp, &bk);
     sh.sb[s] = static_cast<uint16_t>(bk);
@@ -214,7 +217,7 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
   constexpr uint32_t kHitCap = hit_cap<T>();
   static_assert(T % BLOCK == 0 && T <= 65536, "tile shape");
   constexpr int ITER = T / BLOCK;                                     // keys per thread per tile
-  constexpr int SLOTS = (kDenseSlotMax + BLOCK - 1) / BLOCK;          // dense slots per thread
+  constexpr int SLOTS = (dense_slot_cap(T) + BLOCK - 1) / BLOCK;      // dense slots per thread
   __shared__ Sh sh;
   const int tid = threadIdx.x;
   const DenseTab* D = P.dense;
@@ -327,7 +330,7 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
         // here (after the previous barrier), so the decision is uniform.
         const uint32_t sn = __builtin_amdgcn_readfirstlane(sh.stage_n);
         phi = sn;
-        if (sn > static_cast<uint32_t>(Sh::kStage - T / kStageMarginDiv)) {
+        if (sn > static_cast<uint32_t>(Sh::kStage - Sh::kMargin)) {
           build_pending<T, BLOCK>(sh, P, plo, min(sn, static_cast<uint32_t>(Sh::kStage)), px0, pqa, pgrp);
           flush_stage<T, BLOCK>(sh, P);
           plo = phi = 0;
@@ -468,7 +471,8 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
               const uint32_t i = it * BLOCK + tid;
               const uint32_t slot = sbase + __popcll(mask[it] & below);
               if (slot < static_cast<uint32_t>(Sh::kStage)) {
-                sh.stage[slot] = pack_pending(ra[it], rb[it], i);
+                sh.stage[slot] = pack_pending(ra[it], rb[it]);
+                sh.sb[slot] = static_cast<uint16_t>(i);
               } else {
                 uint32_t bk;
                 const Entry e = kept_entry(P, ra[it], rb[it], x0 + i, qa, grp, &bk);

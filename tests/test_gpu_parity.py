@@ -283,7 +283,7 @@ def test_group_invariance(ctx, group):
     assert got == theorem1_pairs(1 << 22)
 
 
-@pytest.mark.parametrize("seg", [4096, 8192, 1 << 17, 1 << 20])
+@pytest.mark.parametrize("seg", [8192, 16384, 1 << 17, 1 << 20])
 def test_segment_length_invariance(ctx, seg):
     ctx.set_option("seg_len", seg)
     try:
@@ -496,7 +496,7 @@ def test_batch_graph_replays_match_eager(ctx):
         assert eager[i] == oracle.search_range(int(a1[i]), int(b1[i]))
 
 
-@pytest.mark.parametrize("tile", [2048, 4096])
+@pytest.mark.parametrize("tile", [2048, 8192])
 def test_tile_invariance(ctx, tile):
     ctx.set_option("tile", tile)
     try:
