@@ -24,10 +24,11 @@ namespace bx {
 constexpr int MODE_RAD = 0;
 constexpr int MODE_KEYS = 1;
 
-// Sparse-hit list held in LDS per segment: 1024 entries with the 2048 tile
-// (two workgroups per CU), 2048 with the 8192 tile.
+// Sparse-hit list held in LDS per segment (about 850 hits per 2^18 values
+// with the 8192 tile, 2050 with the 2048 tile); the excess goes to a global
+// spill list.
 template <int T>
-constexpr int hit_cap() { return T >= 4096 ? 2048 : 1024; }
+constexpr int hit_cap() { return 1024; }
 constexpr int kB1Max = 1024;       // first partition fan-out
 constexpr int kB2Max = 2048;       // second partition fan-out
 constexpr int kPartChunk = 4096;   // entries per workgroup in k_partition
@@ -73,19 +74,27 @@ struct SieveShCommon {
 };
 
 // The stage collects the kept entries of several tiles; it is written out when
-// less than kMargin slots are free at the start of a tile.
+// less than kMargin slots are free at the start of a tile.  A flush runs
+// between tiles, when the tile array is free: its counting sort keeps its
+// histogram, offsets and permutation there (FlushScratch).
 template <int T, int BLOCK>
 struct SieveShKeys : SieveShCommon<T, BLOCK> {
-  // Stage capacity: 4096 entries with the 8192 tile (one workgroup per CU:
+  // Stage capacity: 6016 entries with the 8192 tile (one workgroup per CU:
   // what the LDS leaves beside the 64 KB tile), one tile with the 2048 tile
   // (two per CU).  The margin holds what a tile keeps in the bulk of a range
   // (0.107 T on average, below 0.125 T); a tile that keeps more sends the
   // excess straight to HBM.
-  static constexpr int kStage = T >= 8192 ? 4096 : T;
+  static constexpr int kStage = T >= 8192 ? 6016 : T;
   static constexpr int kMargin = T >= 8192 ? 1152 : T / 4;
   Entry stage[kStage];
-  uint16_t sb[kStage], perm[kStage];
-  uint32_t cnt[kB1Max], gofs[kB1Max], lcur[kB1Max];
+  uint16_t sb[kStage];
+  uint32_t lcur[kB1Max];
+  struct FlushScratch {
+    uint32_t cnt[kB1Max], gofs[kB1Max];
+    uint16_t perm[kStage];
+  };
+  static_assert(sizeof(FlushScratch) <= sizeof(uint64_t) * (T + 1), "flush scratch must fit in the tile");
+  __device__ FlushScratch* flush_scratch() { return reinterpret_cast<FlushScratch*>(this->tile); }
 };
 
 template <int T, int BLOCK, int MODE>
@@ -202,8 +211,9 @@ __device__ void flush_stage(SieveShKeys<T, BLOCK>& sh, const SieveParams& P) {
   const uint64_t cap1 = P.cap1, W = gridDim.x;
   Entry* l1 = P.l1 + static_cast<uint64_t>(blockIdx.x) * cap1;
   const uint16_t* sb = sh.sb;
-  scatter_runs<BLOCK, kB1Max, true>(n, P.b1mask + 1, sh.stage, [=](uint32_t i) -> uint32_t { return sb[i]; }, sh.perm,
-                                    sh.cnt, sh.gofs, sh.wsum, sh.lcur, cap1,
+  auto* fs = sh.flush_scratch();
+  scatter_runs<BLOCK, kB1Max, true>(n, P.b1mask + 1, sh.stage, [=](uint32_t i) -> uint32_t { return sb[i]; }, fs->perm,
+                                    fs->cnt, fs->gofs, sh.wsum, sh.lcur, cap1,
                                     &P.flags[kFlagL1Overflow],
                                     [=](uint32_t b, uint32_t k, const Entry& e) { l1[b * W * cap1 + k] = e; },
                                     [] {});
