@@ -184,9 +184,13 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 // 64-bit hash of a join key: the canonical pair lo < hi (each below 2^43)
 // and, in batched mode, the query id.  Bits 0..10 pick the first-level
 // bucket, bits 11..63 are the entry's fingerprint (whose top bits pick the
-// second-level partition and whose low bits the LDS table slot).
+// second-level partition and whose low bits the LDS table slot).  The word
+// (lo | grp << 43) * K xor hi (K odd) is one-to-one in hi for a fixed lo,
+// and two keys with different lo meet only if the top 21 bits of their
+// products agree and the two hi differ by exactly the xor of the products;
+// the SplitMix64 mix then spreads every bit (three 64-bit products in all).
 __device__ __forceinline__ uint64_t key64(uint64_t lo, uint64_t hi, uint32_t grp) {
-  return mix64((lo | (static_cast<uint64_t>(grp) << 43)) + mix64(hi ^ 0x9E3779B97F4A7C15ull));
+  return mix64(((lo | (static_cast<uint64_t>(grp) << 43)) * 0x9E3779B97F4A7C15ull) ^ hi);
 }
 
 __device__ __forceinline__ uint64_t entry_pos43(const Entry& e) {

@@ -31,7 +31,7 @@ template <int T>
 constexpr int hit_cap() { return 1024; }
 constexpr int kB1Max = 1024;       // first partition fan-out
 constexpr int kB2Max = 2048;       // second partition fan-out
-constexpr int kPartChunk = 4096;   // entries per workgroup in k_partition
+constexpr int kPartChunk = 8192;   // entries per workgroup in k_partition
 constexpr uint32_t kKindThird = 4; // kinds bit: also test rad(m + 2) = rad(n + 2)
 constexpr int kJoinCap = 8192;     // entries of one LDS join chunk (held in registers)
 constexpr int kJoinSlots = 16384;  // LDS hash-table slots (load <= 0.5)
