@@ -204,6 +204,37 @@ __device__ void build_pending(SieveShKeys<T, BLOCK>& sh, const SieveParams& P, u
   }
 }
 
+// Lane mask of the wave's integers x (one per lane, rad(x) = r0 and
+// rad(x + 1) = r1) that pass the member test (may_pair) for the query end qb.
+// UPPER: the tile lies above qb / 2, where no squarefree x or x + 1 passes
+// (the factor t is at least 2), so only both-non-squarefree x remain.  Below,
+// a squarefree y of {x, x + 1} needs y * M <= qb with M = max(2, rad(other)
+// - 1); M > lim_hi fails for the whole segment and settles almost every such
+// y at once, M <= lim_lo passes for the whole segment, and the rare rest take
+// the exact product.  small: the tile starts at x0 <= 3, where x <= 3 is kept.
+template <bool UPPER>
+__device__ __forceinline__ uint64_t member_mask(uint64_t x, uint64_t r0, uint64_t r1, uint64_t lim_hi, uint64_t lim_lo,
+                                                uint64_t qb, bool small) {
+  const bool s0 = r0 == x, s1 = r1 == x + 1;  // x, x + 1 squarefree
+  uint64_t km = ~(__ballot(s0) | __ballot(s1));
+  if constexpr (!UPPER) {
+    const bool c0 = s0 && r1 <= lim_hi + 1, c1 = s1 && r0 <= lim_hi + 1;
+    const uint64_t cm = __ballot(c0 || c1);
+    if (cm) {
+      bool k = false;
+      if (c0 || c1) {
+        const uint64_t M0 = r1 >= 3 ? r1 - 1 : 2, M1 = r0 >= 3 ? r0 - 1 : 2;
+        const bool p0 = !s0 || (c0 && (M0 <= lim_lo || prod_le(x, M0, qb)));
+        const bool p1 = !s1 || (c1 && (M1 <= lim_lo || prod_le(x + 1, M1, qb)));
+        k = p0 && p1;
+      }
+      km = (km & ~cm) | __ballot(k);
+    }
+    if (small) km |= __ballot(x <= 3);
+  }
+  return km;
+}
+
 template <int T, int BLOCK>
 __device__ void flush_stage(SieveShKeys<T, BLOCK>& sh, const SieveParams& P) {
   __syncthreads();
@@ -424,46 +455,43 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
           rb[it] = sh.tile[i + 1];
         }
         // Lane masks of the wave (all 64 lanes are active here): bit l of
-        // mask[it] says whether lane l keeps its it-th integer.
+        // mask[it] says whether lane l keeps its it-th integer.  The common
+        // cases (member test on, one pass, a whole tile) run loops of their
+        // own, so that no uniform flag is tested per integer.
         uint64_t mask[ITER];
         uint32_t total = 0;
         const bool full = cnt == static_cast<uint32_t>(T);
+        const bool small = x0 <= 3;
+        if (P.prune && !P.pfilter && full && upper) {
 #pragma unroll
-        for (int it = 0; it < ITER; ++it) {
-          const uint32_t i = it * BLOCK + tid;
-          const uint64_t r0 = ra[it], r1 = rb[it];
-          const uint64_t x = x0 + i;
-          uint64_t km = ~0ull;
-          if (P.prune) {
-            const bool s0 = r0 == x, s1 = r1 == x + 1;  // x, x + 1 squarefree
-            km = ~(__ballot(s0) | __ballot(s1));
-            if (!upper) {
-              // may_pair: a squarefree y of {x, x + 1} needs y * M <= b with
-              // M = max(2, rad(other) - 1).  M > lim_hi fails for the whole
-              // segment, which settles almost every such y at once; the rest
-              // (M <= lim_hi, i.e. rad(other) <= lim_hi + 1) are taken exactly.
-              const bool c0 = s0 && r1 <= lim_hi + 1, c1 = s1 && r0 <= lim_hi + 1;
-              const uint64_t cm = __ballot(c0 || c1);
-              if (cm) {
-                bool k = false;
-                if (c0 || c1) {
-                  const uint64_t M0 = r1 >= 3 ? r1 - 1 : 2, M1 = r0 >= 3 ? r0 - 1 : 2;
-                  const bool p0 = !s0 || (c0 && (M0 <= lim_lo || prod_le(x, M0, qb)));
-                  const bool p1 = !s1 || (c1 && (M1 <= lim_lo || prod_le(x + 1, M1, qb)));
-                  k = p0 && p1;
-                }
-                km = (km & ~cm) | __ballot(k);
-              }
-              if (x0 <= 3) km |= __ballot(x <= 3);
+          for (int it = 0; it < ITER; ++it) {
+            mask[it] = member_mask<true>(x0 + it * BLOCK + tid, ra[it], rb[it], lim_hi, lim_lo, qb, small);
+            total += __popcll(mask[it]);
+          }
+        } else if (P.prune && !P.pfilter && full) {
+#pragma unroll
+          for (int it = 0; it < ITER; ++it) {
+            mask[it] = member_mask<false>(x0 + it * BLOCK + tid, ra[it], rb[it], lim_hi, lim_lo, qb, small);
+            total += __popcll(mask[it]);
+          }
+        } else {
+#pragma unroll
+          for (int it = 0; it < ITER; ++it) {
+            const uint32_t i = it * BLOCK + tid;
+            const uint64_t r0 = ra[it], r1 = rb[it];
+            const uint64_t x = x0 + i;
+            uint64_t km = ~0ull;
+            if (P.prune)
+              km = upper ? member_mask<true>(x, r0, r1, lim_hi, lim_lo, qb, small)
+                         : member_mask<false>(x, r0, r1, lim_hi, lim_lo, qb, small);
+            if (P.pfilter) {
+              const uint64_t ph = pass_hash(r0 < r1 ? r0 : r1, r0 < r1 ? r1 : r0, grp);
+              km &= __ballot(ph >= P.ph_lo && ph < P.ph_hi);
             }
+            if (!full) km &= __ballot(i < cnt);
+            mask[it] = km;
+            total += __popcll(km);
           }
-          if (P.pfilter) {
-            const uint64_t ph = pass_hash(r0 < r1 ? r0 : r1, r0 < r1 ? r1 : r0, grp);
-            km &= __ballot(ph >= P.ph_lo && ph < P.ph_hi);
-          }
-          if (!full) km &= __ballot(i < cnt);
-          mask[it] = km;
-          total += __popcll(km);
         }
         // 2. Wave-local compaction: ballots rank the wave's kept integers,
         // lane 0 reserves their stage slots with one LDS atomic, and each
@@ -475,25 +503,37 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
           uint32_t sbase = 0;
           if (lane_id() == 0) sbase = atomicAdd(&sh.stage_n, total);
           sbase = __builtin_amdgcn_readfirstlane(sbase);
+          if (sbase + total <= static_cast<uint32_t>(Sh::kStage)) {  // the common case: all in the stage
 #pragma unroll
-          for (int it = 0; it < ITER; ++it) {
-            if ((mask[it] >> lane_id()) & 1ull) {
-              const uint32_t i = it * BLOCK + tid;
-              const uint32_t slot = sbase + __popcll(mask[it] & below);
-              if (slot < static_cast<uint32_t>(Sh::kStage)) {
+            for (int it = 0; it < ITER; ++it) {
+              if ((mask[it] >> lane_id()) & 1ull) {
+                const uint32_t slot = sbase + __popcll(mask[it] & below);
                 sh.stage[slot] = pack_pending(ra[it], rb[it]);
-                sh.sb[slot] = static_cast<uint16_t>(i);
-              } else {
-                uint32_t bk;
-                const Entry e = kept_entry(P, ra[it], rb[it], x0 + i, qa, grp, &bk);
-                const uint32_t g = atomicAdd(&sh.lcur[bk], 1u);
-                if (g < P.cap1)
-                  P.l1[(static_cast<uint64_t>(bk) * gridDim.x + blockIdx.x) * P.cap1 + g] = e;
-                else
-                  atomicOr(&P.flags[kFlagL1Overflow], 1u);
+                sh.sb[slot] = static_cast<uint16_t>(it * BLOCK + tid);
               }
+              sbase += __popcll(mask[it]);
             }
-            sbase += __popcll(mask[it]);
+          } else {
+#pragma unroll
+            for (int it = 0; it < ITER; ++it) {
+              if ((mask[it] >> lane_id()) & 1ull) {
+                const uint32_t i = it * BLOCK + tid;
+                const uint32_t slot = sbase + __popcll(mask[it] & below);
+                if (slot < static_cast<uint32_t>(Sh::kStage)) {
+                  sh.stage[slot] = pack_pending(ra[it], rb[it]);
+                  sh.sb[slot] = static_cast<uint16_t>(i);
+                } else {
+                  uint32_t bk;
+                  const Entry e = kept_entry(P, ra[it], rb[it], x0 + i, qa, grp, &bk);
+                  const uint32_t g = atomicAdd(&sh.lcur[bk], 1u);
+                  if (g < P.cap1)
+                    P.l1[(static_cast<uint64_t>(bk) * gridDim.x + blockIdx.x) * P.cap1 + g] = e;
+                  else
+                    atomicOr(&P.flags[kFlagL1Overflow], 1u);
+                }
+              }
+              sbase += __popcll(mask[it]);
+            }
           }
         }
         plo = phi;  // this tile's slots start where the stage stood at its start
