@@ -259,6 +259,7 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
   static_assert(T % BLOCK == 0 && T <= 65536, "tile shape");
   constexpr int ITER = T / BLOCK;                                     // keys per thread per tile
   constexpr int SLOTS = (dense_slot_cap(T) + BLOCK - 1) / BLOCK;      // dense slots per thread
+  static_assert(kDenseMax <= 64 && T / 9 < 1024, "dense slot packing (sdj below)");
   __shared__ Sh sh;
   const int tid = threadIdx.x;
   const DenseTab* D = P.dense;
@@ -269,22 +270,20 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
   }
   // The dense schedule is the same for every tile: each thread keeps its
   // slots (power index, multiple index, q, p, p^-1) in registers.
-  uint32_t sd[SLOTS], sj[SLOTS], sq[SLOTS], sp[SLOTS], spinv[SLOTS];
+  // sdj = d | j << 6 | p << 16 (d < kDenseMax = 64, j <= T / 9 < 1024,
+  // p <= sqrt(T) < 2^16), packed to leave registers to the tile loop.
+  uint32_t sdj[SLOTS], sq[SLOTS], spinv[SLOTS];
 #pragma unroll
   for (int k = 0; k < SLOTS; ++k) {
     const uint32_t t = tid + k * BLOCK;
     if (t < nslots) {
       const uint32_t d = D->slot_d[t];
-      sd[k] = d;
-      sj[k] = t - D->prefix[d];
+      sdj[k] = d | ((t - D->prefix[d]) << 6) | (D->p[d] << 16);
       sq[k] = D->q[d];
-      sp[k] = D->p[d];
       spinv[k] = D->pinv[d];
     } else {
-      sd[k] = 0;
-      sj[k] = 0;
+      sdj[k] = 1u << 16;
       sq[k] = 0;  // no slot
-      sp[k] = 1;
       spinv[k] = 1;
     }
   }
@@ -317,6 +316,22 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
     const uint64_t start = qa + (s - P.seg_prefix[qi]) * static_cast<uint64_t>(P.seg_len);
     const uint32_t len = static_cast<uint32_t>(min(static_cast<uint64_t>(P.seg_len), qb - start));
     const uint64_t V = start + len;  // largest value sieved in this segment
+    // Every tile starts at x0 = qa (mod T) (segments and tiles are multiples
+    // of T), so the factor-2 shift of x = x0 + j, j = it * BLOCK + tid, is
+    // max(ctz(m), 1) - 1 with m = (qa + j) mod T, the same in every tile,
+    // except at the one j with m = 0 (ctz(x) >= log2 T), taken exactly.
+    // Four bits per integer of this thread.
+    const uint32_t c2 = static_cast<uint32_t>(qa) & static_cast<uint32_t>(T - 1);
+    const uint32_t sp_j = (static_cast<uint32_t>(T) - c2) & static_cast<uint32_t>(T - 1);
+    uint32_t shifts = 0;
+    if constexpr (MODE == MODE_KEYS) {
+#pragma unroll
+      for (int it = 0; it < ITER; ++it) {
+        const uint32_t m = (c2 + static_cast<uint32_t>(it * BLOCK + tid)) & static_cast<uint32_t>(T - 1);
+        const uint32_t tz = m ? static_cast<uint32_t>(__builtin_ctz(m)) : 1u;
+        shifts |= (max(tz, 1u) - 1u) << (4 * it);
+      }
+    }
     // Member test below b/2: y * M <= b fails for every y of the segment when
     // M > lim_hi and holds for every y when M <= lim_lo (y in [start, V]);
     // only M in between needs the exact product.  Both limits are
@@ -381,9 +396,15 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
       const uint64_t x0 = start + base;
       // r[n] <- n with the prime 2 already reduced (count trailing zeros).
       // The whole tile is written (values past cnt are never used).
-      // Uniform: no x of the tile (x0 .. x0 + T) has a zero low word.
-      const uint32_t x0lo = static_cast<uint32_t>(x0);
-      if (x0lo != 0u && x0lo <= 0xFFFFFFFFu - static_cast<uint32_t>(T)) {
+      if constexpr (MODE == MODE_KEYS) {
+#pragma unroll
+        for (int it = 0; it < ITER; ++it)
+          sh.tile[it * BLOCK + tid] = (x0 + it * BLOCK + tid) >> ((shifts >> (4 * it)) & 15u);
+        if (static_cast<uint32_t>(tid) == (sp_j & static_cast<uint32_t>(BLOCK - 1))) sh.tile[sp_j] = strip_two(x0 + sp_j);
+        if (tid == 0) sh.tile[T] = strip_two(x0 + T);
+      } else if (const uint32_t x0lo = static_cast<uint32_t>(x0);
+                 x0lo != 0u && x0lo <= 0xFFFFFFFFu - static_cast<uint32_t>(T)) {
+        // Uniform: no x of the tile (x0 .. x0 + T) has a zero low word.
 #pragma unroll
         for (int it = 0; it < ITER; ++it) sh.tile[it * BLOCK + tid] = strip_two_lo(x0 + it * BLOCK + tid);
         if (tid == 0) sh.tile[T] = strip_two_lo(x0 + T);
@@ -408,8 +429,8 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
 #pragma unroll
       for (int k = 0; k < SLOTS; ++k) {
         if (sq[k] == 0) continue;
-        const uint32_t pos = sh.doff[sd[k]] + sj[k] * sq[k];
-        if (pos <= cnt) lds_div(&sh.tile[pos], sp[k], spinv[k]);
+        const uint32_t pos = sh.doff[sdj[k] & 63u] + ((sdj[k] >> 6) & 1023u) * sq[k];
+        if (pos <= cnt) lds_div(&sh.tile[pos], sdj[k] >> 16, spinv[k]);
       }
       // Sparse hits of this tile: the LDS list, then the rare spill.
       const uint32_t nh_lds = min(nh, kHitCap);
