@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--parse-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into " + TRAFFIC_FILE)
     ap.add_argument("--cpu-sample-log2", type=int, default=22)
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the 4096-query batched workload (--warmup + --steps launches of its graph), "
+                         "for a kernel trace of that workload")
     return ap.parse_args()
 
 
@@ -230,6 +233,9 @@ def main():
 
     from paper_2506_01099_amd import Benelux
 
+    if args.only_batched:
+        run_batched_only(args)
+        return
     N = 1 << args.log2n
     if args.calib:
         calib_copy()
@@ -336,6 +342,31 @@ def run_batched(bx):
             "plain_contiguous_integers_per_s": total_L / t_plain,
             "one_by_one_integers_per_s": L_sample / t_seq_sample, "one_by_one_sample_queries": int(idx.size),
             "kernel_ms": st["kernel_ms"], "passes": st["passes"]}
+
+
+def run_batched_only(args):
+    from paper_2506_01099_amd import Benelux
+    from paper_2506_01099_amd.inputs import batched_queries
+
+    bx = Benelux(device=0)
+    if os.path.exists(args.tuning):
+        bx.load_tuning(args.tuning)
+    a, b = batched_queries()
+    total_L = int((b - a).sum())
+    for i in range(args.warmup):
+        log(f"warmup {i + 1}/{args.warmup}: batch of {a.size} queries")
+        bx.search_batch(a, b)
+    times = []
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        bx.search_batch(a, b)
+        times.append(time.perf_counter() - t0)
+        log(f"step {i + 1}/{args.steps}: {times[-1] * 1e3:.2f} ms")
+    st = bx.stats()
+    bx.close()
+    print(json.dumps({"workload": f"batched: {a.size} range queries, {total_L} integers", "steps": args.steps,
+                      "ms_per_batch": [t * 1e3 for t in times], "integers_per_s": total_L / min(times),
+                      "graph_ms": st["graph_ms"], "passes": st["passes"]}), flush=True)
 
 
 def run_served(bx, seconds):
