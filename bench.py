@@ -409,9 +409,32 @@ def run_served(bx, seconds):
     srv.stop()
     lat = np.array([v[0] for v in done.values()])
     total_L = int((b - a).sum())
-    return {"requests": int(t.size), "integers": total_L, "wall_s": t_end - t_start,
-            "integers_per_s": total_L / (t_end - t_start), "p50_ms": float(np.percentile(lat, 50) * 1e3),
-            "p99_ms": float(np.percentile(lat, 99) * 1e3), "pairs": int(sum(v[1] for v in done.values()))}
+    out = {"requests": int(t.size), "integers": total_L, "wall_s": t_end - t_start,
+           "integers_per_s": total_L / (t_end - t_start), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+           "p99_ms": float(np.percentile(lat, 99) * 1e3), "pairs": int(sum(v[1] for v in done.values()))}
+    out["fifo_plain"] = run_fifo(bx, t, a, b)
+    return out
+
+
+def run_fifo(bx, t, a, b):
+    """The same trace on the plain range path, FIFO, one request at a time: each
+    search starts at its arrival or when the previous one ends, whichever is later."""
+    import numpy as np
+
+    lat = []
+    n_pairs = 0
+    t_start = time.perf_counter()
+    for i in range(t.size):
+        wait = t_start + t[i] - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        n_pairs += len(bx.search_range(int(a[i]), int(b[i])))
+        lat.append(time.perf_counter() - (t_start + t[i]))
+    wall = time.perf_counter() - t_start
+    lat = np.array(lat)
+    return {"requests": int(t.size), "wall_s": wall, "integers_per_s": int((b - a).sum()) / wall,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "pairs": n_pairs}
 
 
 if __name__ == "__main__":
