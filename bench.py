@@ -64,16 +64,29 @@ def parse():
     return ap.parse_args()
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(N, log2_sample):
     import oracle
 
     S = 1 << log2_sample
     a = max(1, N - S)
-    threads = os.cpu_count() or 1
+    # The host cores this process may run on, capped at 16.
+    threads = max(1, min(len(os.sched_getaffinity(0)), 16))
     t0 = time.perf_counter()
     pairs, t_rad, t_join = oracle.search_range_timed(a, N + 1, 3, threads)
     dt = time.perf_counter() - t0
     return {"value": (N + 1 - a) / dt, "unit": "integers/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"oracle.search_range over x in [{a}, {N + 1}) ({N + 1 - a} integers at magnitude 2^{int(math.log2(N))}); "
                       f"radicals {t_rad:.2f} s on {threads} threads, hash-map join {t_join:.2f} s on 1 thread",
             "seconds": dt}

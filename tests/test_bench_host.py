@@ -115,3 +115,12 @@ def test_stale_counters_are_not_reported(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.json"))
     assert bench.load_traffic() == {}
 
+
+
+def test_cpu_baseline_reports_its_sample_cores_and_cpu():
+    cb = bench.cpu_baseline(1 << 20, 12)  # 4097 integers: milliseconds
+    assert cb["kind"] == "oracle" and cb["unit"] == "integers/s"
+    assert 1 <= cb["cores"] <= 16
+    assert cb["value"] > 0 and cb["seconds"] > 0
+    assert "[1044480, 1048577)" in cb["sample"]
+    assert "cpu_model" in cb
