@@ -58,6 +58,11 @@ def parse():
     ap.add_argument("--parse-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into " + TRAFFIC_FILE)
     ap.add_argument("--cpu-sample-log2", type=int, default=22)
+    ap.add_argument("--only-served", type=float, default=0.0, metavar="SECONDS",
+                    help="run only the served trace for SECONDS (no FIFO replay), for a kernel trace of that workload")
+    ap.add_argument("--trace-overlap", metavar="TRACE_DIR",
+                    help="device time during which kernels of two or more streams ran at once, from a "
+                         "rocprofv3 --kernel-trace output directory")
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the 4096-query batched workload (--warmup + --steps launches of its graph), "
                          "for a kernel trace of that workload")
@@ -249,8 +254,21 @@ def main():
 
     from paper_2506_01099_amd import Benelux
 
+    if args.trace_overlap:
+        print(json.dumps(trace_overlap(args.trace_overlap)))
+        return
     if args.only_batched:
         run_batched_only(args)
+        return
+    if args.only_served > 0:
+        from paper_2506_01099_amd import Benelux
+
+        bx = Benelux(device=0)
+        if os.path.exists(args.tuning):
+            bx.load_tuning(args.tuning)
+        out = run_served(bx, args.only_served, fifo=False)
+        bx.close()
+        print(json.dumps(out), flush=True)
         return
     N = 1 << args.log2n
     if args.calib:
@@ -394,7 +412,36 @@ def run_batched_only(args):
                       "graph_ms": st["graph_ms"], "passes": st["passes"]}), flush=True)
 
 
-def run_served(bx, seconds):
+def trace_overlap(d):
+    """From a kernel trace: the device time with at least one kernel running (busy)
+    and the part of it with kernels of two or more streams running at once."""
+    import csv
+    import glob
+
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            stream = (r.get("Stream_Id"), r.get("Queue_Id"))
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), stream))
+    # Sweep over start/end events: per stream the number of running kernels.
+    ev = sorted([(t0, 1, st) for t0, t1, st in rows] + [(t1, -1, st) for t0, t1, st in rows],
+                key=lambda e: (e[0], e[1]))
+    running, busy, overlap, last = {}, 0, 0, None
+    for t, delta, st in ev:
+        if last is not None:
+            active = sum(1 for v in running.values() if v > 0)
+            if active >= 1:
+                busy += t - last
+            if active >= 2:
+                overlap += t - last
+        running[st] = running.get(st, 0) + delta
+        last = t
+    streams = sorted({str(st) for _, _, st in rows})
+    return {"kernels": len(rows), "streams": streams, "busy_ms": busy / 1e6, "overlap_ms": overlap / 1e6,
+            "overlap_frac_of_busy": overlap / busy if busy else None}
+
+
+def run_served(bx, seconds, fifo=True):
     import numpy as np
 
     from paper_2506_01099_amd import Server
@@ -425,7 +472,8 @@ def run_served(bx, seconds):
     out = {"requests": int(t.size), "integers": total_L, "wall_s": t_end - t_start,
            "integers_per_s": total_L / (t_end - t_start), "p50_ms": float(np.percentile(lat, 50) * 1e3),
            "p99_ms": float(np.percentile(lat, 99) * 1e3), "pairs": int(sum(v[1] for v in done.values()))}
-    out["fifo_plain"] = run_fifo(bx, t, a, b)
+    if fifo:
+        out["fifo_plain"] = run_fifo(bx, t, a, b)
     return out
 
 

@@ -124,3 +124,22 @@ def test_cpu_baseline_reports_its_sample_cores_and_cpu():
     assert cb["value"] > 0 and cb["seconds"] > 0
     assert "[1044480, 1048577)" in cb["sample"]
     assert "cpu_model" in cb
+
+
+def test_trace_overlap_counts_time_with_two_streams_running(tmp_path):
+    # Stream A runs [0, 100) and [300, 400) ns; stream B runs [50, 150) and [160, 170) ns
+    # (two kernels of one stream that touch do not count as overlap).
+    rows = [(0, 100, 1), (300, 400, 1), (50, 150, 2), (160, 170, 2), (170, 180, 2)]
+    with open(tmp_path / "run_kernel_trace.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Queue_Id", "Stream_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for t0, t1, st in rows:
+            w.writerow({"Queue_Id": st, "Stream_Id": st, "Kernel_Name": "k", "Start_Timestamp": t0,
+                        "End_Timestamp": t1})
+    out = bench.trace_overlap(str(tmp_path))
+    assert out["kernels"] == 5
+    assert len(out["streams"]) == 2
+    # Busy: [0, 150) + [160, 180) + [300, 400) = 270 ns; two streams at once: [50, 100) = 50 ns.
+    assert out["busy_ms"] == pytest.approx(270e-6)
+    assert out["overlap_ms"] == pytest.approx(50e-6)
+    assert out["overlap_frac_of_busy"] == pytest.approx(50 / 270)
