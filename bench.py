@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--trace-overlap", metavar="TRACE_DIR",
                     help="device time during which kernels of two or more streams ran at once, from a "
                          "rocprofv3 --kernel-trace output directory")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the autotuner on the 4096-query batched workload and write its result to --tuning")
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the 4096-query batched workload (--warmup + --steps launches of its graph), "
                          "for a kernel trace of that workload")
@@ -256,6 +258,17 @@ def main():
 
     if args.trace_overlap:
         print(json.dumps(trace_overlap(args.trace_overlap)))
+        return
+    if args.autotune:
+        from paper_2506_01099_amd import Benelux
+        from paper_2506_01099_amd.inputs import batched_queries
+
+        bx = Benelux(device=0)
+        a, b = batched_queries()
+        log(f"autotuning on {a.size} batched queries ...")
+        bx.autotune(a, b, reps=2, path=args.tuning)
+        bx.close()
+        print(open(args.tuning).read().strip(), flush=True)
         return
     if args.only_batched:
         run_batched_only(args)
