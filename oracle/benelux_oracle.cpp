@@ -21,6 +21,13 @@
 //     empty one), and unlike the adjacent-only comparison printed in
 //     Algorithm 2, which would skip the pair (2,8) of the group {2,3,8}.
 //
+//   * Erdos's original question (abstract and Section 1) adds a third
+//     condition, rad(m+2) = rad(n+2).  With the kinds bit 4 a first-kind pair
+//     that also meets rad(m+d) = rad(n+d) is reported with kind 5 (= 1 | 4);
+//     d = 2 is the question as asked, other offsets d serve the tests (d = 1
+//     repeats the second condition, so every first-kind pair meets it).  The
+//     two radicals are taken by trial division, the definition.
+//
 // Ranges: a range query [a, b) reports pairs with max(a,1) <= m < n < b, so it
 // needs radicals over [max(a,1), b].  search(N) is the range [1, N+1): pairs
 // with n <= N.  Zero is not a positive integer and is never part of a range.
@@ -109,13 +116,16 @@ int orc_radicals(uint64_t lo, uint64_t hi, uint64_t* out, int threads) {
 }
 
 // All pairs max(a,1) <= m < n < b whose kind is in the mask `kinds`
-// (1 = first, 2 = second, 3 = both), sorted by (m, n).  *out is malloc'd and
-// released with orc_free.  Timings of the two phases go to t_rad / t_join
-// (seconds) when those pointers are non-null.  Returns 0, or -1 on bad args,
-// -3 when memory runs out.
-int orc_search_range(uint64_t a, uint64_t b, uint32_t kinds, int threads, orc_pair** out, size_t* count,
-                     double* t_rad, double* t_join) {
-  if (!out || !count || kinds < 1 || kinds > 3) return -1;
+// (1 = first, 2 = second, 4 = first kind and the third condition with offset
+// third_offset, reported as kind 5; any mask in 1..7), sorted by (m, n).  A
+// pair is reported when its kind (1 or 2) is in the mask, or when bit 4 is set
+// and it is a first-kind pair with rad(m + d) = rad(n + d), d = third_offset;
+// its kind is then 5.  *out is malloc'd and released with orc_free.  Timings
+// of the two phases go to t_rad / t_join (seconds) when those pointers are
+// non-null.  Returns 0, or -1 on bad args, -3 when memory runs out.
+int orc_search_range_ex(uint64_t a, uint64_t b, uint32_t kinds, uint32_t third_offset, int threads, orc_pair** out,
+                        size_t* count, double* t_rad, double* t_join) {
+  if (!out || !count || kinds < 1 || kinds > 7) return -1;
   *out = nullptr;
   *count = 0;
   if (a == 0) a = 1;
@@ -148,7 +158,13 @@ int orc_search_range(uint64_t a, uint64_t b, uint32_t kinds, int threads, orc_pa
         for (size_t j = i + 1; j < xs.size(); ++j) {
           const uint64_t m = std::min(xs[i], xs[j]), n = std::max(xs[i], xs[j]);
           const uint32_t kind = (r[m - a] == r[n - a]) ? 1u : 2u;
-          if (kinds & kind) pairs.push_back({m, n, kind, 0u});
+          // Third condition (Section 1): only a first-kind pair can meet all three.
+          const bool third = (kinds & 4u) && kind == 1u &&
+                             rad_trial(m + third_offset) == rad_trial(n + third_offset);
+          if (third)
+            pairs.push_back({m, n, kind | 4u, 0u});
+          else if (kinds & kind)
+            pairs.push_back({m, n, kind, 0u});
         }
     }
   } catch (...) {
@@ -169,6 +185,13 @@ int orc_search_range(uint64_t a, uint64_t b, uint32_t kinds, int threads, orc_pa
   }
   *count = pairs.size();
   return 0;
+}
+
+// The two kinds only (mask 1..3), as Algorithm 2 reports them.
+int orc_search_range(uint64_t a, uint64_t b, uint32_t kinds, int threads, orc_pair** out, size_t* count,
+                     double* t_rad, double* t_join) {
+  if (kinds > 3) return -1;
+  return orc_search_range_ex(a, b, kinds, 2, threads, out, count, t_rad, t_join);
 }
 
 void orc_free(void* p) { std::free(p); }

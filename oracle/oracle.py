@@ -46,6 +46,11 @@ def _load():
                                          ctypes.POINTER(ctypes.c_size_t),
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         lib.orc_search_range.restype = ctypes.c_int
+        lib.orc_search_range_ex.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                            ctypes.c_int, ctypes.POINTER(ctypes.POINTER(_Pair)),
+                                            ctypes.POINTER(ctypes.c_size_t),
+                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        lib.orc_search_range_ex.restype = ctypes.c_int
         lib.orc_free.argtypes = [ctypes.c_void_p]
         lib.orc_free.restype = None
         _lib = lib
@@ -71,18 +76,24 @@ def radicals(lo, hi, threads=0):
     return out
 
 
-def search_range_timed(a, b, kinds=3, threads=0):
-    """(pairs, t_radicals_s, t_join_s); pairs sorted list of (m, n, kind), max(a,1) <= m < n < b."""
-    if kinds not in (1, 2, 3):
-        raise ValueError("kinds must be 1, 2 or 3")
+def search_range_timed(a, b, kinds=3, threads=0, third_offset=2):
+    """(pairs, t_radicals_s, t_join_s); pairs sorted list of (m, n, kind), max(a,1) <= m < n < b.
+
+    kinds is a mask in 1..7: 1 first kind, 2 second kind, 4 a first-kind pair that
+    also has rad(m + third_offset) = rad(n + third_offset), reported as kind 5
+    (third_offset = 2 is Erdos's third condition)."""
+    if kinds not in range(1, 8):
+        raise ValueError("kinds must be a mask in 1..7")
+    if third_offset < 0:
+        raise ValueError("third_offset must be >= 0")
     p = ctypes.POINTER(_Pair)()
     cnt = ctypes.c_size_t(0)
     tr, tj = ctypes.c_double(0.0), ctypes.c_double(0.0)
     lib = _load()
-    rc = lib.orc_search_range(int(a), int(b), int(kinds), int(threads), ctypes.byref(p), ctypes.byref(cnt),
-                              ctypes.byref(tr), ctypes.byref(tj))
+    rc = lib.orc_search_range_ex(int(a), int(b), int(kinds), int(third_offset), int(threads), ctypes.byref(p),
+                                 ctypes.byref(cnt), ctypes.byref(tr), ctypes.byref(tj))
     if rc != 0:
-        raise RuntimeError(f"orc_search_range failed ({rc})")
+        raise RuntimeError(f"orc_search_range_ex failed ({rc})")
     try:
         pairs = [(int(p[i].m), int(p[i].n), int(p[i].kind)) for i in range(cnt.value)]
     finally:
@@ -91,10 +102,10 @@ def search_range_timed(a, b, kinds=3, threads=0):
     return pairs, tr.value, tj.value
 
 
-def search_range(a, b, kinds=3, threads=0):
-    return search_range_timed(a, b, kinds, threads)[0]
+def search_range(a, b, kinds=3, threads=0, third_offset=2):
+    return search_range_timed(a, b, kinds, threads, third_offset)[0]
 
 
-def search(N, kinds=3, threads=0):
+def search(N, kinds=3, threads=0, third_offset=2):
     """All pairs 1 <= m < n <= N (radicals over [1, N+1])."""
-    return search_range(1, N + 1, kinds, threads)
+    return search_range(1, N + 1, kinds, threads, third_offset)

@@ -250,3 +250,52 @@ def test_no_listed_first_kind_pair_meets_the_third_condition():
             assert m + 2 == 2 ** k and (n + 2) % 4 == 2
             assert oracle.rad(m + 2) == 2 and oracle.rad(n + 2) != 2
         assert oracle.rad(m + 2) != oracle.rad(n + 2)
+
+
+def _bruteforce_third(N, d, r):
+    """First-kind pairs m < n <= N (Section 1's definition) that also have
+    rad(m + d) = rad(n + d), straight from the definition over radicals r."""
+    out = []
+    for m in range(1, N):
+        n = np.arange(m + 1, N + 1)
+        first = (r[n] == r[m]) & (r[n + 1] == r[m + 1]) & (r[n + d] == r[m + d])
+        out += [(m, int(k)) for k in n[first]]
+    return out
+
+
+@pytest.mark.parametrize("d", [0, 1, 2, 3, 4, 5, 6, 8])
+def test_third_condition_bruteforce(d):
+    """Kinds bit 4 with offset d against the definition for every m < n <= 2^12
+    (radicals from a smallest-prime-factor sieve).  d = 2 is Erdos's question: no
+    pair; d = 0 and d = 1 repeat the first two conditions: every first-kind pair."""
+    N = 2**12
+    r = spf_radicals(N + 9)
+    want = _bruteforce_third(N, d, r)
+    got = oracle.search(N, kinds=4, third_offset=d)
+    assert got == [(m, n, 5) for m, n in want]
+    firsts = [(m, n) for m, n, k in theorem1_pairs(N) if k == 1]
+    if d in (0, 1):
+        assert want == firsts
+    if d == 2:
+        assert want == []
+    # The full mask: pairs meeting the third condition carry kind 5, the rest keep 1 or 2.
+    full = oracle.search(N, kinds=7, third_offset=d)
+    marked = set(want)
+    assert full == [(m, n, 5 if (m, n) in marked else k) for m, n, k in theorem1_pairs(N)]
+    assert oracle.search(N, kinds=5, third_offset=d) == [p for p in full if p[2] in (1, 5)]
+    assert oracle.search(N, kinds=6, third_offset=d) == [p for p in full if p[2] in (2, 5)]
+
+
+def test_third_condition_nontrivial_offset():
+    """Offset 4 marks (2, 8) only (rad 6 = rad 12) among the pairs up to 2^12, so the
+    marking is not all-or-nothing; worked out by hand from the factorizations."""
+    assert oracle.search(2**12, kinds=4, third_offset=4) == [(2, 8, 5)]
+    assert oracle.rad(6) == oracle.rad(12) == 6
+
+
+def test_third_condition_range_and_default():
+    """Range form and the default offset 2 (Erdos's question): nothing up to 2^20."""
+    assert oracle.search(2**20, kinds=4) == []
+    assert oracle.search(2**20, kinds=7) == oracle.search(2**20, kinds=3)
+    assert oracle.search_range(3, 4000, kinds=4, third_offset=1) == [
+        (m, n, 5) for m, n, k in theorem1_pairs(4000) if k == 1 and m >= 3]

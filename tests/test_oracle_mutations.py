@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 from paper_facts import theorem1_pairs
-from test_oracle import spf_radicals, squarefree_count
+from test_oracle import _bruteforce_third, spf_radicals, squarefree_count
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "benelux_oracle.cpp")
 
@@ -27,6 +27,9 @@ MUTATIONS = {
     "kinds_swapped": ("(r[m - a] == r[n - a]) ? 1u : 2u", "(r[m - a] == r[n - a]) ? 2u : 1u"),
     "missing_overlap_value": ("radicals_mt(a, b + 1, r.data(), threads);", "radicals_mt(a, b, r.data(), threads);"),
     "two_kept_twice": ("    while ((x & 1) == 0) x >>= 1;\n", "    x >>= 1;\n"),
+    "third_offset_off_by_one": ("rad_trial(n + third_offset)", "rad_trial(n + third_offset + 1)"),
+    "third_fixed_offset": ("rad_trial(m + third_offset)", "rad_trial(m + 2)"),
+    "third_marks_without_kind_bit": ("pairs.push_back({m, n, kind | 4u, 0u});", "pairs.push_back({m, n, kind, 0u});"),
 }
 
 
@@ -39,6 +42,9 @@ class Mutant:
         self.lib.orc_search_range.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int,
                                               ctypes.POINTER(ctypes.POINTER(oracle.oracle._Pair)),
                                               ctypes.POINTER(ctypes.c_size_t), ctypes.c_void_p, ctypes.c_void_p]
+        self.lib.orc_search_range_ex.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                                 ctypes.c_int, ctypes.POINTER(ctypes.POINTER(oracle.oracle._Pair)),
+                                                 ctypes.POINTER(ctypes.c_size_t), ctypes.c_void_p, ctypes.c_void_p]
         self.lib.orc_free.argtypes = [ctypes.c_void_p]
 
     def radicals(self, lo, hi):
@@ -46,10 +52,11 @@ class Mutant:
         self.lib.orc_radicals(lo, hi, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), 2)
         return out
 
-    def search_range(self, a, b):
+    def search_range(self, a, b, kinds=3, third_offset=2):
         p = ctypes.POINTER(oracle.oracle._Pair)()
         c = ctypes.c_size_t(0)
-        assert self.lib.orc_search_range(a, b, 3, 2, ctypes.byref(p), ctypes.byref(c), None, None) == 0
+        assert self.lib.orc_search_range_ex(a, b, kinds, third_offset, 2, ctypes.byref(p), ctypes.byref(c),
+                                            None, None) == 0
         res = [(int(p[i].m), int(p[i].n), int(p[i].kind)) for i in range(c.value)]
         if c.value:
             self.lib.orc_free(p)
@@ -71,6 +78,16 @@ def pins_pass(m):
     x = np.arange(1, (1 << 16) + 1, dtype=np.uint64)
     if int(np.count_nonzero(m.radicals(1, (1 << 16) + 1) == x)) != squarefree_count(1 << 16):
         return False
+    # Third condition: brute force by the definition for the offsets 1, 2, 4.
+    rr = spf_radicals(4097 + 8)
+    for d in (1, 2, 4):
+        want = [(a, b, 5) for a, b in _bruteforce_third(4096, d, rr)]
+        if m.search_range(1, 4097, kinds=4, third_offset=d) != want:
+            return False
+        marked = {(a, b) for a, b, _ in want}
+        full = [(a, b, 5 if (a, b) in marked else k) for a, b, k in theorem1_pairs(4096)]
+        if m.search_range(1, 4097, kinds=7, third_offset=d) != full:
+            return False
     return True
 
 
