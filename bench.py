@@ -72,14 +72,33 @@ def parse():
 
 
 def cpu_model():
+    """The host CPU as /proc/cpuinfo names it: model name, family, model and stepping."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if ":" not in line:
+                    if info:
+                        break
+                    continue
+                k, v = (t.strip() for t in line.split(":", 1))
+                if k in ("vendor_id", "model name", "cpu family", "model", "stepping", "cpu MHz") and k not in info:
+                    info[k] = v
     except OSError:
-        pass
-    return None
+        return None
+    return (f"{info.get('model name', '?')} (vendor {info.get('vendor_id', '?')}, family {info.get('cpu family', '?')}, "
+            f"model {info.get('model', '?')}, stepping {info.get('stepping', '?')}, {info.get('cpu MHz', '?')} MHz)")
+
+
+def host_threads():
+    """Threads for the oracle: the CPU share given to this process (OMP_NUM_THREADS when the
+    environment sets it, as it does for one GPU's share of a shared host), else every core of
+    the process's affinity mask."""
+    aff = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return min(aff, int(env)), aff
+    return aff, aff
 
 
 def cpu_baseline(N, log2_sample):
@@ -87,13 +106,13 @@ def cpu_baseline(N, log2_sample):
 
     S = 1 << log2_sample
     a = max(1, N - S)
-    # The host cores this process may run on, capped at 16.
-    threads = max(1, min(len(os.sched_getaffinity(0)), 16))
+    threads, host_cpus = host_threads()
     t0 = time.perf_counter()
     pairs, t_rad, t_join = oracle.search_range_timed(a, N + 1, 3, threads)
     dt = time.perf_counter() - t0
     return {"value": (N + 1 - a) / dt, "unit": "integers/s", "cores": threads, "kind": "oracle",
-            "cpu_model": cpu_model(),
+            "cpu_model": cpu_model(), "host_cpus_in_affinity": host_cpus,
+            "os_cpu_count": os.cpu_count(), "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
             "sample": f"oracle.search_range over x in [{a}, {N + 1}) ({N + 1 - a} integers at magnitude 2^{int(math.log2(N))}); "
                       f"radicals {t_rad:.2f} s on {threads} threads, hash-map join {t_join:.2f} s on 1 thread",
             "seconds": dt}

@@ -118,7 +118,7 @@ int bx_search_batch(bx_ctx* ctx, const uint64_t* a, const uint64_t* b, size_t q,
  * (malloc'd) and releases the ticket.  Times are seconds on the library's
  * monotonic clock (bx_now).  Each of the max_inflight lanes is a context of
  * its own that takes the owner's search options (tile, seg_len, prune,
- * join, fp_bits, group) as they are when serving starts. */
+ * join, fp_bits, third_offset, group) as they are when serving starts. */
 int bx_serve_start(bx_ctx* ctx, uint64_t budget_bytes, int max_inflight);
 int bx_serve_stop(bx_ctx* ctx);
 int bx_submit(bx_ctx* ctx, uint64_t a, uint64_t b, uint32_t kinds, uint64_t* ticket);
@@ -154,6 +154,8 @@ typedef struct {
   uint32_t b1_bits, b2_bits;  /* partition fan-outs used                          */
   uint32_t seg_len, tile;     /* segment length and LDS tile used by the sieve    */
   double graph_ms;            /* device time of the captured graph (batched calls) */
+  uint64_t joined;            /* entries the join kernels read (equals entries)   */
+  uint64_t false_candidates;  /* candidates whose sets differ (dropped by verify) */
 } bx_stats;
 int bx_get_stats(bx_ctx* ctx, bx_stats* out);
 
@@ -173,6 +175,10 @@ int bx_get_stats(bx_ctx* ctx, bx_stats* out);
  *   "join"         0 = LDS hash join per partition (default), 1 = sort join per
  *                  partition (Algorithm 2 on each partition, every pair of a
  *                  run of equal keys reported; an ablation)
+ *   "third_offset" for tests of the third condition: compare rad(m + d) and
+ *                  rad(n + d) with d = value (in [0, 64]) instead of d = 2,
+ *                  so that kinds bit BX_THIRD marks known pairs (d = 0 or 1
+ *                  marks every first-kind pair; default 2)
  *   "prune"        1 = only integers that can be a member of a pair enter the
  *                  join (default 1; the pair lists are the same either way:
  *                  a pair's larger member n has n and n+1 non-squarefree, and

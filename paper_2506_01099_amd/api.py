@@ -70,6 +70,7 @@ class Benelux:
             "launches": dict(zip(names, list(st.launches))), "kernel_ms": dict(zip(names, list(st.kernel_ms))),
             "total_ms": st.total_ms, "b1_bits": st.b1_bits, "b2_bits": st.b2_bits,
             "seg_len": st.seg_len, "tile": st.tile, "graph_ms": st.graph_ms,
+            "joined": st.joined, "false_candidates": st.false_candidates,
         }
 
     def autotune(self, a, b, reps=1, path=None):

@@ -110,6 +110,7 @@ struct bx_ctx {
   int force_passes = 0, timing = 1, force_b1 = -1, force_b2 = -1, force_group = 0;
   int prune = 1;            // drop x that cannot be a pair member before the join
   int join_sort = 0;        // 1: the sort join per partition (ablation of the hash join)
+  uint32_t third_off = 2;   // offset d of the third condition rad(m + d) = rad(n + d); 2 is Erdős's
   // Fingerprint bits kept: all 53 in use; tests keep the top 11 (the
   // partition bits) and a few low ones to make different sets collide.
   uint64_t fp_mask = (1ull << kFpBits) - 1;
@@ -556,8 +557,8 @@ SieveParams base_sieve_params(bx_ctx* c, const Segs& s) {
 }
 
 int check_query(const bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds) {
-  // The third condition needs rad(n + 2) <= hi_max + 1 by trial division.
-  const uint64_t top = (kinds & BX_THIRD) ? b + 1 : b;
+  // The third condition takes rad(n + d), n <= b - 1, by trial division.
+  const uint64_t top = (kinds & BX_THIRD) ? std::max<uint64_t>(b, b - 1 + c->third_off) : b;
   if (top > c->hi_max || top >= BX_VALUE_LIMIT)
     return fail(BX_ERANGE, "range end " + std::to_string(b) + " exceeds hi_max " + std::to_string(c->hi_max));
   (void)a;
@@ -717,6 +718,7 @@ int enqueue_verify(bx_ctx* c, const Job& j, uint32_t grid, hipStream_t st) {
   V.queries = static_cast<const Query*>(c->queries.p);
   V.batch = j.batch;
   V.kinds = j.kinds;
+  V.third_off = c->third_off;
   V.fp_mask = c->fp_mask;
   V.out = static_cast<OutPair*>(c->out.p);
   V.out_cap = kCandCap;
@@ -742,6 +744,8 @@ int collect_pairs(bx_ctx* c, const uint32_t* fl, hipStream_t st, std::vector<Out
   if (fl[kFlagVerifyFail])
     return fail(BX_EINTERNAL, std::to_string(fl[kFlagVerifyFail]) + " candidate pairs failed exact verification");
   c->stats.candidates = fl[kFlagCand];
+  c->stats.joined = fl[kFlagJoined];
+  c->stats.false_candidates = fl[kFlagFalseCand];
   const uint32_t n_out = std::min(fl[kFlagOut], kCandCap);
   c->stats.pairs = n_out;
   result->resize(n_out);
@@ -770,7 +774,7 @@ int run_passes_checked(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* 
   std::deque<std::pair<uint64_t, uint64_t>> pending;
   for (uint64_t v = 0; v < j.plan.passes; ++v)
     pending.emplace_back((v << 32) / j.plan.passes, ((v + 1) << 32) / j.plan.passes);
-  uint32_t cand_before = 0;
+  uint32_t cand_before = 0, joined_before = 0;
   unsigned long long acc_before = 0;
   uint32_t fl[kFlagCount];
   while (!pending.empty()) {
@@ -787,6 +791,7 @@ int run_passes_checked(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* 
       uint32_t z[2] = {0, 0};
       BX_HIP(hipMemcpyAsync(d_flags + kFlagL1Overflow, z, sizeof(z), hipMemcpyHostToDevice, st));
       BX_HIP(hipMemcpyAsync(d_flags + kFlagCand, &cand_before, 4, hipMemcpyHostToDevice, st));
+      BX_HIP(hipMemcpyAsync(d_flags + kFlagJoined, &joined_before, 4, hipMemcpyHostToDevice, st));
       BX_HIP(hipMemcpyAsync(c->acc.p, &acc_before, 8, hipMemcpyHostToDevice, st));
       BX_HIP(hipStreamSynchronize(st));
       const uint64_t mid = ph_lo + (ph_hi - ph_lo) / 2;
@@ -795,6 +800,7 @@ int run_passes_checked(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* 
       continue;
     }
     cand_before = fl[kFlagCand];
+    joined_before = fl[kFlagJoined];
     BX_HIP(hipMemcpyAsync(&acc_before, c->acc.p, 8, hipMemcpyDeviceToHost, st));
     BX_HIP(hipStreamSynchronize(st));
   }
@@ -818,10 +824,10 @@ int run_passes_graph(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* re
   // Every launch shape, every option baked into a kernel argument or choice,
   // and every buffer address the graph's kernels use.
   std::snprintf(key, sizeof(key),
-                "%u %llu %u %u %u %u %llu %u %d %u %d %u %d %d %llx %p %p %p %p %p %p %p %p %p %p %p %p %p",
+                "%u %llu %u %u %u %u %llu %u %d %u %u %d %u %d %d %llx %p %p %p %p %p %p %p %p %p %p %p %p %p",
                 j.plan.passes, static_cast<unsigned long long>(j.plan.cap1), j.plan.cap2, j.plan.b1bits, j.plan.b2bits,
                 j.G, static_cast<unsigned long long>(j.s->n_segs), static_cast<uint32_t>(j.s->q.size()), j.batch,
-                j.kinds, c->tile, c->seg_len, c->prune, c->join_sort,
+                j.kinds, c->third_off, c->tile, c->seg_len, c->prune, c->join_sort,
                 static_cast<unsigned long long>(c->fp_mask), c->l1.p, c->l2.p, c->spill.p, c->cnt1.p, c->cnt2.p,
                 c->cand.p, c->out.p, c->flags.p, c->acc.p, c->queries.p, c->segpref.p, static_cast<void*>(c->d_pp),
                 static_cast<void*>(c->d_primes));
@@ -1137,6 +1143,9 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
       return fail(BX_EINVAL, "fp_bits must be 0 or in [12, 53]");
     const uint64_t all = (1ull << kFpBits) - 1;
     c->fp_mask = (v == 0 || v >= 42) ? all : (all & ~((1ull << 42) - 1)) | ((1ull << v) - 1);
+  } else if (n == "third_offset") {
+    if (v < 0 || v > 64) return fail(BX_EINVAL, "third_offset must be in [0, 64]");
+    c->third_off = static_cast<uint32_t>(v);
   } else if (n == "group") {
     if (v != 0 && v != 1 && v != 2 && v != 4 && v != 8) return fail(BX_EINVAL, "group must be 0, 1, 2, 4 or 8");
     c->force_group = static_cast<int>(v);
@@ -1291,6 +1300,7 @@ int bx_serve_start(bx_ctx* c, uint64_t budget_bytes, int max_inflight) {
     lane->prune = c->prune;
     lane->join_sort = c->join_sort;
     lane->fp_mask = c->fp_mask;
+    lane->third_off = c->third_off;
     lane->force_group = c->force_group;
     lane->timing = 0;
     lane->graph_batch = 0;  // batch shapes change from batch to batch: no graph reuse

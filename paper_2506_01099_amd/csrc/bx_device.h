@@ -70,6 +70,7 @@ enum : int {
   kFlagVerifyFail = 4,
   kFlagSpillOverflow = 5,
   kFlagFalseCand = 6,  // equal fingerprints of different sets (dropped)
+  kFlagJoined = 7,     // entries read by the join kernels (one add per partition)
   kFlagCount = 8
 };
 

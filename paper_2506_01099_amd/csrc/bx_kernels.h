@@ -718,7 +718,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
   const uint32_t n = min(P.cnt2[sbk], P.cap2);
   __syncthreads();
   // This workgroup is the only reader of the cursor: clear it for the next group.
-  if (tid == 0) P.cnt2[sbk] = 0;
+  if (tid == 0) {
+    P.cnt2[sbk] = 0;
+    if (n) atomicAdd(&P.flags[kFlagJoined], n);
+  }
   if (n < 2) return;
   const Entry* src = P.l2 + sbk * P.cap2;
   for (uint32_t i0 = 0; i0 < n; i0 += kJoinCap) {
@@ -812,7 +815,10 @@ __global__ __launch_bounds__(BLOCK) void k_join_sort(JoinParams P) {
   const uint32_t n = min(P.cnt2[sbk], P.cap2);
   __syncthreads();
   // This workgroup is the only reader of the cursor: clear it for the next group.
-  if (tid == 0) P.cnt2[sbk] = 0;
+  if (tid == 0) {
+    P.cnt2[sbk] = 0;
+    if (n) atomicAdd(&P.flags[kFlagJoined], n);
+  }
   if (n < 2) return;
   const Entry* src = P.l2 + sbk * P.cap2;
   auto same = [&](const Entry& a, const Entry& b) {
@@ -883,6 +889,7 @@ struct VerifyParams {
   const Query* queries;
   int batch;
   uint32_t kinds;
+  uint32_t third_off;  // the third condition compares rad(m + third_off), rad(n + third_off) (2 in use)
   uint64_t fp_mask;
   OutPair* out;
   uint32_t out_cap;
@@ -894,7 +901,7 @@ struct VerifyParams {
 // every prime <= sqrt(v) being 1 or one more prime.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_verify(VerifyParams P) {
-  constexpr int NV = 6;  // m, m+1, n, n+1 and, for the third condition, m+2, n+2
+  constexpr int NV = 6;  // m, m+1, n, n+1 and, for the third condition, m+d, n+d (d = 2)
   __shared__ uint64_t red_r[NV][BLOCK], red_s[NV][BLOCK];
   const int tid = threadIdx.x;
   const uint32_t n_cand = min(*P.n_cand, P.cand_cap);
@@ -907,8 +914,9 @@ __global__ __launch_bounds__(BLOCK) void k_verify(VerifyParams P) {
     const uint64_t off = P.batch ? P.queries[qa_idx].a : 0ull;
     const uint64_t xa = entry_pos(cd.a, P.batch) + off, xb = entry_pos(cd.b, P.batch) + off;
     const uint64_t m = xa < xb ? xa : xb, n = xa < xb ? xb : xa;
-    const uint64_t v[NV] = {m, m + 1, n, n + 1, m + 2, n + 2};
-    const uint64_t vmax = third ? n + 2 : n + 1;
+    const uint64_t d = P.third_off;
+    const uint64_t v[NV] = {m, m + 1, n, n + 1, m + d, n + d};
+    const uint64_t vmax = third && d > 1 ? n + d : n + 1;
     uint64_t pr[NV] = {1, 1, 1, 1, 1, 1}, sm[NV] = {1, 1, 1, 1, 1, 1};
     for (uint32_t i = tid; i < P.n_primes; i += BLOCK) {
       const uint64_t p = P.primes[i];
