@@ -63,9 +63,10 @@ def fp_mask(fp_bits):
 
 def kept(x, r0, r1, b):
     """Member test: x (with r0 = rad(x), r1 = rad(x + 1)) can belong to a pair m < n < b.
-    int64 arrays; exact while x * r stays below 2^63."""
-    drop0 = (r0 == x) & (x * np.maximum(2, r1 - 1) > b)
-    drop1 = (r1 == x + 1) & ((x + 1) * np.maximum(2, r0 - 1) > b)
+    int64 arrays.  y * M > b is taken as M > floor(b / y) (y >= 1), which is exact and
+    cannot overflow: the product itself passes 2^63 once y and M are near 2^32."""
+    drop0 = (r0 == x) & (np.maximum(2, r1 - 1) > b // x)
+    drop1 = (r1 == x + 1) & (np.maximum(2, r0 - 1) > b // (x + 1))
     return (x <= 3) | ~(drop0 | drop1)
 
 
