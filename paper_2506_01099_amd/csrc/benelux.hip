@@ -617,7 +617,7 @@ int prepare_job(bx_ctx* c, Segs& s, int batch, uint32_t kinds, hipStream_t st, J
   if ((rc = ensure(c, c->cand, kCandCap * sizeof(Cand))) != BX_OK) return rc;
   if ((rc = ensure(c, c->out, kCandCap * sizeof(OutPair))) != BX_OK) return rc;
   if ((rc = ensure(c, c->flags, kFlagCount * 4)) != BX_OK) return rc;
-  if ((rc = ensure(c, c->acc, 8)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->acc, kAccCount * sizeof(unsigned long long))) != BX_OK) return rc;
   if ((rc = ensure(c, c->spill, static_cast<size_t>(j->sieve_grid) * spill_cap_of(c) * 8)) != BX_OK) return rc;
   if ((rc = upload_segs(c, s, st)) != BX_OK) return rc;
   c->stats.b1_bits = plan.b1bits;
@@ -632,7 +632,7 @@ int enqueue_init(bx_ctx* c, const Job& j, hipStream_t st) {
   int rc;
   if ((rc = fill_u32(c, c->flags.p, kFlagCount, 0, st)) != BX_OK) return rc;
   if ((rc = fill_u32(c, c->cnt2.p, j.ngsub, 0, st)) != BX_OK) return rc;
-  if ((rc = fill_u32(c, c->acc.p, 2, 0, st)) != BX_OK) return rc;
+  if ((rc = fill_u32(c, c->acc.p, 2 * kAccCount, 0, st)) != BX_OK) return rc;
   return BX_OK;
 }
 
@@ -658,7 +658,7 @@ int enqueue_pass(bx_ctx* c, const Job& j, uint64_t ph_lo, uint64_t ph_hi, hipStr
   }
   BX_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_sum_counts, dim3(64), dim3(256), 0, st, static_cast<const uint32_t*>(c->cnt1.p), j.n_regions,
-                     static_cast<unsigned long long*>(c->acc.p));
+                     static_cast<unsigned long long*>(c->acc.p) + kAccEntries);
   BX_HIP(hipGetLastError());
   for (uint32_t first = 0; first < j.B1; first += j.G) {
     PartParams Q;
@@ -696,6 +696,7 @@ int enqueue_pass(bx_ctx* c, const Job& j, uint64_t ph_lo, uint64_t ph_hi, hipStr
     J.cand = static_cast<Cand*>(c->cand.p);
     J.cand_cap = kCandCap;
     J.flags = d_flags;
+    J.joined = static_cast<unsigned long long*>(c->acc.p) + kAccJoined;
     {
       LaunchTimer t(c, K_JOIN, st);
       if (c->join_sort)
@@ -744,7 +745,6 @@ int collect_pairs(bx_ctx* c, const uint32_t* fl, hipStream_t st, std::vector<Out
   if (fl[kFlagVerifyFail])
     return fail(BX_EINTERNAL, std::to_string(fl[kFlagVerifyFail]) + " candidate pairs failed exact verification");
   c->stats.candidates = fl[kFlagCand];
-  c->stats.joined = fl[kFlagJoined];
   c->stats.false_candidates = fl[kFlagFalseCand];
   const uint32_t n_out = std::min(fl[kFlagOut], kCandCap);
   c->stats.pairs = n_out;
@@ -753,10 +753,11 @@ int collect_pairs(bx_ctx* c, const uint32_t* fl, hipStream_t st, std::vector<Out
     BX_HIP(hipMemcpyAsync(result->data(), c->out.p, n_out * sizeof(OutPair), hipMemcpyDeviceToHost, st));
     BX_HIP(hipStreamSynchronize(st));
   }
-  unsigned long long entries = 0;
-  BX_HIP(hipMemcpyAsync(&entries, c->acc.p, 8, hipMemcpyDeviceToHost, st));
+  unsigned long long acc[kAccCount] = {0, 0};
+  BX_HIP(hipMemcpyAsync(acc, c->acc.p, sizeof(acc), hipMemcpyDeviceToHost, st));
   BX_HIP(hipStreamSynchronize(st));
-  c->stats.entries = entries;
+  c->stats.entries = acc[kAccEntries];
+  c->stats.joined = acc[kAccJoined];
   std::sort(result->begin(), result->end(), [](const OutPair& x, const OutPair& y) {
     if (x.query != y.query) return x.query < y.query;
     if (x.m != y.m) return x.m < y.m;
@@ -774,8 +775,8 @@ int run_passes_checked(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* 
   std::deque<std::pair<uint64_t, uint64_t>> pending;
   for (uint64_t v = 0; v < j.plan.passes; ++v)
     pending.emplace_back((v << 32) / j.plan.passes, ((v + 1) << 32) / j.plan.passes);
-  uint32_t cand_before = 0, joined_before = 0;
-  unsigned long long acc_before = 0;
+  uint32_t cand_before = 0;
+  unsigned long long acc_before[kAccCount] = {0, 0};
   uint32_t fl[kFlagCount];
   while (!pending.empty()) {
     const uint64_t ph_lo = pending.front().first, ph_hi = pending.front().second;
@@ -791,8 +792,7 @@ int run_passes_checked(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* 
       uint32_t z[2] = {0, 0};
       BX_HIP(hipMemcpyAsync(d_flags + kFlagL1Overflow, z, sizeof(z), hipMemcpyHostToDevice, st));
       BX_HIP(hipMemcpyAsync(d_flags + kFlagCand, &cand_before, 4, hipMemcpyHostToDevice, st));
-      BX_HIP(hipMemcpyAsync(d_flags + kFlagJoined, &joined_before, 4, hipMemcpyHostToDevice, st));
-      BX_HIP(hipMemcpyAsync(c->acc.p, &acc_before, 8, hipMemcpyHostToDevice, st));
+      BX_HIP(hipMemcpyAsync(c->acc.p, acc_before, sizeof(acc_before), hipMemcpyHostToDevice, st));
       BX_HIP(hipStreamSynchronize(st));
       const uint64_t mid = ph_lo + (ph_hi - ph_lo) / 2;
       pending.emplace_front(mid, ph_hi);
@@ -800,8 +800,7 @@ int run_passes_checked(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* 
       continue;
     }
     cand_before = fl[kFlagCand];
-    joined_before = fl[kFlagJoined];
-    BX_HIP(hipMemcpyAsync(&acc_before, c->acc.p, 8, hipMemcpyDeviceToHost, st));
+    BX_HIP(hipMemcpyAsync(acc_before, c->acc.p, sizeof(acc_before), hipMemcpyDeviceToHost, st));
     BX_HIP(hipStreamSynchronize(st));
   }
   if (cand_before > 0) {

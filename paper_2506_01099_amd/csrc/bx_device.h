@@ -70,9 +70,12 @@ enum : int {
   kFlagVerifyFail = 4,
   kFlagSpillOverflow = 5,
   kFlagFalseCand = 6,  // equal fingerprints of different sets (dropped)
-  kFlagJoined = 7,     // entries read by the join kernels (one add per partition)
-  kFlagCount = 8
+  kFlagCount = 7
 };
+
+// 64-bit per-call counters (acc[]): entries written by the sieve, entries read
+// by the join kernels (one add per partition).
+enum : int { kAccEntries = 0, kAccJoined = 1, kAccCount = 2 };
 
 // Exact quotient r / p for an odd prime p dividing r, r < 2^64, from
 // p^{-1} mod 2^32 (division by an invariant integer via its inverse,

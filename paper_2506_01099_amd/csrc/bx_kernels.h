@@ -683,6 +683,7 @@ struct JoinParams {
   Cand* cand;
   uint32_t cand_cap;
   uint32_t* flags;
+  unsigned long long* joined;  // entries read, summed over partitions (64-bit: 2^36 searches pass 2^32)
 };
 
 __device__ __forceinline__ void emit_cand(const JoinParams& P, const Entry& a, const Entry& b) {
@@ -720,7 +721,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
   // This workgroup is the only reader of the cursor: clear it for the next group.
   if (tid == 0) {
     P.cnt2[sbk] = 0;
-    if (n) atomicAdd(&P.flags[kFlagJoined], n);
+    if (n) atomicAdd(P.joined, static_cast<unsigned long long>(n));
   }
   if (n < 2) return;
   const Entry* src = P.l2 + sbk * P.cap2;
@@ -817,7 +818,7 @@ __global__ __launch_bounds__(BLOCK) void k_join_sort(JoinParams P) {
   // This workgroup is the only reader of the cursor: clear it for the next group.
   if (tid == 0) {
     P.cnt2[sbk] = 0;
-    if (n) atomicAdd(&P.flags[kFlagJoined], n);
+    if (n) atomicAdd(P.joined, static_cast<unsigned long long>(n));
   }
   if (n < 2) return;
   const Entry* src = P.l2 + sbk * P.cap2;
