@@ -92,6 +92,25 @@ int bx_radical_segment(bx_ctx* ctx, uint64_t lo, uint64_t hi, uint64_t* out);
  * are queued; the caller synchronises the stream. */
 int bx_radical_segment_dev(bx_ctx* ctx, uint64_t lo, uint64_t hi, uint64_t* dev_out, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * bx_radical_segment_dev without any allocation.  Its kernels keep their
+ * scratch (counter words, the query table, the sparse-hit spill of at most
+ * 512 sieve workgroups x 4096 hits) in one fixed device array of about 16 MB
+ * that the library holds on every device it runs on until the process ends;
+ * nothing is allocated or freed by the call (the context's prime tables come
+ * from bx_create).  Arguments, layout and ownership as bx_radical_segment_dev.
+ * Unlike it, the call returns after its kernels have finished (it reads back
+ * the overflow word).  Errors: those of bx_radical_segment_dev; BX_ENOMEM
+ * before any launch when the context's segment length would need more than
+ * half the scratch's sparse-hit room on average (at most 2^19 with the 8192
+ * tile, 2^18 with the 2048 tile), and BX_ENOMEM after the launch if a segment
+ * overflowed it anyway (dev_out is then incomplete).  Calls on one device share
+ * its scratch and keep the last call's contents; the library serialises them
+ * (a per-device lock held until the kernels have finished), so they do not
+ * race, but they do not overlap either. */
+int bx_radical_segment_dev_noalloc(bx_ctx* ctx, uint64_t lo, uint64_t hi, uint64_t* dev_out, void* hip_stream);
+
 /* All pairs 1 <= m < n <= N whose kind is in `kinds` (Algorithm 2's output,
  * found by the hash-partitioned join); radicals are sieved over [1, N + 1].
  * *out is malloc'd, *count set.  N + 1 <= hi_max. */

@@ -16,7 +16,7 @@ _NAMES = {BX_EINVAL: "BX_EINVAL", BX_ERANGE: "BX_ERANGE", BX_ENOMEM: "BX_ENOMEM"
 # Every symbol declared in include/benelux.h.
 EXPORTS = [
     "bx_create", "bx_destroy", "bx_set_stream", "bx_radical_segment", "bx_radical_segment_dev",
-    "bx_benelux_search", "bx_search_range", "bx_search_batch", "bx_serve_start", "bx_serve_stop",
+    "bx_radical_segment_dev_noalloc", "bx_benelux_search", "bx_search_range", "bx_search_batch", "bx_serve_start", "bx_serve_stop",
     "bx_submit", "bx_poll", "bx_take", "bx_now", "bx_get_stats", "bx_set_option", "bx_free",
     "bx_autotune", "bx_load_tuning",
     "bx_last_error", "benelux_search", "radical_segment",
@@ -74,6 +74,7 @@ def load():
         "bx_set_stream": ([vp, vp], ctypes.c_int),
         "bx_radical_segment": ([vp, u64, u64, P64], ctypes.c_int),
         "bx_radical_segment_dev": ([vp, u64, u64, vp, vp], ctypes.c_int),
+        "bx_radical_segment_dev_noalloc": ([vp, u64, u64, vp, vp], ctypes.c_int),
         "bx_benelux_search": ([vp, u64, u32, PP, ctypes.POINTER(sz)], ctypes.c_int),
         "bx_search_range": ([vp, u64, u64, u32, PP, ctypes.POINTER(sz)], ctypes.c_int),
         "bx_search_batch": ([vp, P64, P64, sz, u32, PP, ctypes.POINTER(sz)], ctypes.c_int),

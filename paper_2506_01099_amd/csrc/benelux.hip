@@ -102,6 +102,7 @@ struct bx_ctx {
   std::string arch;
   std::vector<uint32_t> primes;
   std::vector<PrimePow> pp;
+  std::vector<double> cum_inv_q;  // cum_inv_q[i] = sum of 1/q over pp[0, i)
   uint32_t n_dense[2] = {0, 0};  // per tile shape (small, large)
   uint32_t* d_primes = nullptr;
   PrimePow* d_pp = nullptr;
@@ -126,6 +127,7 @@ struct bx_ctx {
   std::vector<TimedLaunch> timed;
   hipEvent_t last_done = nullptr;    // recorded after the last call's work
   hipStream_t last_stream = nullptr;  // stream that work ran on
+  void* na = nullptr;  // this device's no-allocation scratch (NaDevice)
   // serving
   struct Server;
   std::unique_ptr<Server> server;
@@ -256,6 +258,8 @@ int build_tables(bx_ctx* c) {
     }
   }
   std::sort(c->pp.begin(), c->pp.end(), [](const PrimePow& a, const PrimePow& b) { return a.q < b.q; });
+  c->cum_inv_q.assign(c->pp.size() + 1, 0.0);
+  for (size_t i = 0; i < c->pp.size(); ++i) c->cum_inv_q[i + 1] = c->cum_inv_q[i] + c->pp[i].invq;
   for (int which = 0; which < 2; ++which) {
     const uint32_t T = which ? kTileLarge : kTileSmall;
     DenseTab dt;
@@ -930,6 +934,45 @@ int radicals_into(bx_ctx* c, uint64_t lo, uint64_t hi, uint64_t* dev_out, hipStr
   return BX_OK;
 }
 
+// Scratch of bx_radical_segment_dev_noalloc: the counter words, the one-query
+// table and the sparse-hit spill of up to kNaGrid sieve workgroups, in one
+// fixed device array (every device the library runs on holds its own copy
+// until the process ends).  Host code reaches it only through the address
+// hipGetSymbolAddress returns on each device.
+constexpr uint32_t kNaGrid = 512;   // sieve workgroups of one call at most
+constexpr uint32_t kNaSpill = 4096; // spilled sparse hits per workgroup (beyond the LDS list)
+constexpr size_t kNaQueryOff = 256, kNaPrefOff = 512, kNaSpillOff = 1024;
+constexpr size_t kNaBytes = kNaSpillOff + static_cast<size_t>(kNaGrid) * kNaSpill * sizeof(uint64_t);
+static_assert(kFlagCount * sizeof(uint32_t) <= kNaQueryOff && sizeof(Query) <= kNaPrefOff - kNaQueryOff,
+              "scratch layout");
+static __device__ __align__(256) uint8_t scratch[kNaBytes];
+
+struct NaDevice {
+  std::mutex mu;             // serialises the calls that use this device's scratch
+  uint8_t* ptr = nullptr;    // device address of `scratch` on this device
+};
+std::mutex g_na_mu;
+std::map<int, std::unique_ptr<NaDevice>> g_na;
+
+// Once per device, with that device current: the device address of its copy
+// of the scratch array.
+int na_setup(int device, NaDevice** out) {
+  std::lock_guard<std::mutex> lk(g_na_mu);
+  auto& slot = g_na[device];
+  if (!slot) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(BX_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    slot.reset(new NaDevice());
+    slot->ptr = static_cast<uint8_t*>(p);
+  }
+  *out = slot.get();
+  return BX_OK;
+}
+
 std::mutex g_default_mu;
 bx_ctx* g_default = nullptr;
 
@@ -1082,6 +1125,9 @@ int bx_create(bx_ctx** out, int device, uint64_t hi_max, uint64_t hbm_budget_byt
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : static_cast<uint64_t>(0.85 * static_cast<double>(free_b));
   int rc = build_tables(c.get());
   if (rc != BX_OK) return rc;
+  NaDevice* na = nullptr;
+  if ((rc = na_setup(device, &na)) != BX_OK) return rc;
+  c->na = na;
   *out = c.release();
   return BX_OK;
 }
@@ -1207,6 +1253,82 @@ int bx_radical_segment_dev(bx_ctx* c, uint64_t lo, uint64_t hi, uint64_t* dev_ou
   c->stats.integers = hi - lo;
   if (rc == BX_OK) rc = mark_done(c, st);
   return rc;
+}
+
+int bx_radical_segment_dev_noalloc(bx_ctx* c, uint64_t lo, uint64_t hi, uint64_t* dev_out, void* stream) {
+  if (!c) return fail(BX_EINVAL, "ctx is NULL");
+  if (lo == 0 || hi < lo) return fail(BX_EINVAL, "need 1 <= lo <= hi");
+  if (hi > lo && !dev_out) return fail(BX_EINVAL, "dev_out is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  reset_stats(c);
+  int rc = check_query(c, lo, hi, 0);
+  if (rc != BX_OK) return rc;
+  if (hi == lo) return BX_OK;
+  // The sparse hits of one segment average seg_len * (sum of 1/q over the
+  // sparse powers q <= hi); the LDS list and this workgroup's share of the
+  // scratch must hold twice that.
+  const int which = c->tile == kTileLarge ? 1 : 0;
+  const uint32_t first_sparse = c->n_dense[which];
+  const size_t top = static_cast<size_t>(
+      std::upper_bound(c->pp.begin(), c->pp.end(), hi, [](uint64_t v, const PrimePow& w) { return v < w.q; }) -
+      c->pp.begin());
+  const double expect = static_cast<double>(c->seg_len) *
+                        (c->cum_inv_q[std::max<size_t>(top, first_sparse)] - c->cum_inv_q[first_sparse]);
+  const double room = static_cast<double>(hit_cap<kTileLarge>() + kNaSpill);
+  if (2.0 * expect > room)
+    return fail(BX_ENOMEM, "segment length " + std::to_string(c->seg_len) + " needs about " +
+                               std::to_string(static_cast<uint64_t>(expect)) +
+                               " sparse hits per segment; the fixed scratch holds " +
+                               std::to_string(static_cast<uint64_t>(room)) + " (use bx_radical_segment_dev)");
+  BX_HIP(hipSetDevice(c->device));
+  NaDevice* na = static_cast<NaDevice*>(c->na);
+  std::lock_guard<std::mutex> lk_na(na->mu);
+  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  if ((rc = order_after_last(c, st)) != BX_OK) return rc;
+  uint32_t* flags = reinterpret_cast<uint32_t*>(na->ptr);
+  Query* q = reinterpret_cast<Query*>(na->ptr + kNaQueryOff);
+  uint64_t* pref = reinterpret_cast<uint64_t*>(na->ptr + kNaPrefOff);
+  const uint64_t n_segs = (hi - lo + c->seg_len - 1) / c->seg_len;
+  const uint32_t grid = static_cast<uint32_t>(
+      std::min<uint64_t>({n_segs, kNaGrid, 2ull * sieve_wg_per_cu(c) * static_cast<uint64_t>(c->n_cu)}));
+  // The counters start at zero (a fill kernel), the query table is written
+  // from kernel arguments.
+  if ((rc = fill_u32(c, flags, kFlagCount, 0, st)) != BX_OK) return rc;
+  hipLaunchKernelGGL(k_set_query, dim3(1), dim3(64), 0, st, q, pref, lo, hi, n_segs);
+  BX_HIP(hipGetLastError());
+  SieveParams P;
+  std::memset(&P, 0, sizeof(P));
+  P.queries = q;
+  P.seg_prefix = pref;
+  P.n_queries = 1;
+  P.n_segs = n_segs;
+  P.seg_len = c->seg_len;
+  P.pp = c->d_pp;
+  P.n_pp = static_cast<uint32_t>(c->pp.size());
+  P.n_dense = first_sparse;
+  P.dense = c->d_dense[which];
+  P.spill = reinterpret_cast<uint64_t*>(na->ptr + kNaSpillOff);
+  P.spill_cap = kNaSpill;
+  P.flags = flags;
+  P.rad_out = dev_out;
+  P.rad_lo = lo;
+  P.rad_hi = hi;
+  c->stats.launches[K_RAD]++;
+  launch_sieve<MODE_RAD>(c, P, grid, st);
+  BX_HIP(hipGetLastError());
+  // The call waits for its kernels: the overflow word is read back, and the
+  // next call may reuse the scratch.
+  uint32_t overflow = 0;
+  BX_HIP(hipMemcpyAsync(&overflow, flags + kFlagSpillOverflow, sizeof(overflow), hipMemcpyDeviceToHost, st));
+  BX_HIP(hipStreamSynchronize(st));
+  if (c->last_done) {
+    BX_HIP(hipEventRecord(c->last_done, st));
+    c->last_stream = st;
+  }
+  c->stats.integers = hi - lo;
+  if (overflow)
+    return fail(BX_ENOMEM, "sparse-hit scratch overflow: dev_out is incomplete (use bx_radical_segment_dev)");
+  return BX_OK;
 }
 
 int bx_search_range(bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds, bx_pair** out, size_t* count) {

@@ -16,6 +16,7 @@
 //                       sets are dropped here), classified (first kind when
 //                       rad(m) = rad(n), Algorithm 2) and filtered by kind.
 //   k_fill_u32          fills a word array (clears counters inside graphs).
+//   k_set_query         writes a one-query table from kernel arguments.
 #pragma once
 #include "bx_device.h"
 
@@ -994,6 +995,17 @@ __global__ void k_sum_counts(const uint32_t* cnt, uint64_t n, unsigned long long
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
     s += cnt[i];
   if (s) atomicAdd(acc, static_cast<unsigned long long>(s));
+}
+
+// The one-query table of a single-range sieve, written from kernel arguments
+// (no host copy).
+__global__ void k_set_query(Query* q, uint64_t* seg_prefix, uint64_t a, uint64_t b, uint64_t n_segs) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    q->a = a;
+    q->b = b;
+    seg_prefix[0] = 0;
+    seg_prefix[1] = n_segs;
+  }
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
