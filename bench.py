@@ -44,8 +44,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--log2n", type=int, default=36)
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-query batched workload")
-    ap.add_argument("--served", type=float, default=10.0,
-                    help="seconds of the served trace to replay (0 = skip)")
+    ap.add_argument("--served", type=float, default=60.0,
+                    help="seconds of the served trace to replay (0 = skip; 60 = all 12,000 requests)")
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2506_01099_amd", "tuning_gfx950.json"),
                     help="autotuner result to load for the batched and served runs (if present)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -53,6 +53,8 @@ def parse():
                     help="skip the comparison run with the member test off")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the sort-join ablation run")
+    ap.add_argument("--no-paper-schedule", action="store_true",
+                    help="skip Algorithm 3's chunk schedule at 2^32 (the paper's design, a baseline)")
     ap.add_argument("--calib", action="store_true",
                     help="first copy 4 GiB with a plain copy kernel (reference for HBM counters)")
     ap.add_argument("--parse-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -371,6 +373,30 @@ def main():
         line["sort_join_ablation"] = {"integers_per_s": N / total1, "ms_per_step": total1 * 1e3,
                                       "join_ms": agg1["kernel_ms"]["join"],
                                       "hash_join_ms": line["kernel_ms_per_step"]["join"]}
+    if not args.no_paper_schedule:
+        # The paper's own design (Algorithm 3: chunks of 2^27 overlapping by one, a table of
+        # 2^29 slots per chunk, every earlier chunk sieved again) on this GPU at 2^32, beside
+        # the hash-partitioned passes on the same range; the pair lists must agree.
+        log("paper schedule (Algorithm 3) at 2^32 ...")
+        N32 = 1 << 32
+        t0 = time.perf_counter()
+        p_hash = bx.search(N32)
+        t_hash = time.perf_counter() - t0
+        bx.set_option("schedule", 1)
+        try:
+            t0 = time.perf_counter()
+            p_a3 = bx.search(N32)
+            t_a3 = time.perf_counter() - t0
+            st_a3 = bx.stats()
+        finally:
+            bx.set_option("schedule", 0)
+        if p_a3 != p_hash:
+            raise SystemExit("pair lists differ between Algorithm 3's schedule and the hash-partitioned passes")
+        line["paper_schedule_2p32"] = {"seconds": t_a3, "integers_per_s": N32 / t_a3, "chunks": st_a3["passes"],
+                                       "chunk": 1 << 27, "table_slots": 1 << 29,
+                                       "radicals_ms": st_a3["kernel_ms"]["radicals"],
+                                       "insert_probe_ms": st_a3["kernel_ms"]["join"],
+                                       "hash_partitioned_seconds": t_hash, "pairs": len(p_a3)}
     if not args.no_batched or args.served > 0:
         if os.path.exists(args.tuning):
             bx.load_tuning(args.tuning)
@@ -473,7 +499,13 @@ def trace_overlap(d):
             "overlap_frac_of_busy": overlap / busy if busy else None}
 
 
-def run_served(bx, seconds, fifo=True):
+def run_served(bx, seconds, fifo=True, budget_bytes=200 << 30, max_inflight=2):
+    """Replays the served trace (its first `seconds`, or all of it) through the serving
+    calls.  A submitter thread submits each request at its arrival time; latency is the
+    library's completion time minus the arrival time, and the submit lag (the library's
+    submit time minus the arrival time) is reported beside it."""
+    import threading
+
     import numpy as np
 
     from paper_2506_01099_amd import Server
@@ -482,28 +514,55 @@ def run_served(bx, seconds, fifo=True):
     t, a, b = served_trace(n=12000)
     keep = t < seconds
     t, a, b = t[keep], a[keep], b[keep]
-    srv = Server(bx, budget_bytes=200 << 30, max_inflight=2)
-    tickets = []
-    t_start = srv.now()
-    i = 0
-    done = {}
-    while len(done) < t.size:
-        now = srv.now() - t_start
-        while i < t.size and t[i] <= now:
-            tickets.append((srv.submit(int(a[i]), int(b[i])), t_start + t[i]))
-            i += 1
-        for tk, arr in tickets:
-            if tk not in done and srv.poll(tk):
-                pairs, ts, td = srv.take(tk)
-                done[tk] = (td - arr, len(pairs))
-        time.sleep(0.0005)
+    srv = Server(bx, budget_bytes=budget_bytes, max_inflight=max_inflight)
+    tickets = [None] * t.size
+    submitted = threading.Semaphore(0)
+    t_start = srv.now() + 0.05
+
+    def submitter():
+        for i in range(t.size):
+            while True:
+                wait = t_start + t[i] - srv.now()
+                if wait <= 0:
+                    break
+                time.sleep(wait if wait < 0.002 else wait - 0.001)
+            tickets[i] = srv.submit(int(a[i]), int(b[i]))
+            submitted.release()
+
+    th = threading.Thread(target=submitter, daemon=True)
+    th.start()
+    lat, lag, svc, n_pairs = [], [], [], 0
+    pending = []
+    n_sub = 0
+    while len(lat) < t.size:
+        while submitted.acquire(blocking=False):
+            pending.append(n_sub)
+            n_sub += 1
+        still = []
+        for i in pending:
+            if srv.poll(tickets[i]):
+                pairs, ts, td = srv.take(tickets[i])
+                arr = t_start + t[i]
+                lat.append(td - arr)
+                lag.append(ts - arr)
+                svc.append(td - ts)
+                n_pairs += len(pairs)
+            else:
+                still.append(i)
+        pending = still
+        time.sleep(0.0002)
+    th.join()
     t_end = srv.now()
+    info = srv.info()
     srv.stop()
-    lat = np.array([v[0] for v in done.values()])
+    lat, lag, svc = np.array(lat), np.array(lag), np.array(svc)
     total_L = int((b - a).sum())
+    pc = lambda v, q: float(np.percentile(v, q) * 1e3)
     out = {"requests": int(t.size), "integers": total_L, "wall_s": t_end - t_start,
-           "integers_per_s": total_L / (t_end - t_start), "p50_ms": float(np.percentile(lat, 50) * 1e3),
-           "p99_ms": float(np.percentile(lat, 99) * 1e3), "pairs": int(sum(v[1] for v in done.values()))}
+           "integers_per_s": total_L / (t_end - t_start), "p50_ms": pc(lat, 50), "p99_ms": pc(lat, 99),
+           "submit_lag_p50_ms": pc(lag, 50), "submit_lag_p99_ms": pc(lag, 99),
+           "service_p50_ms": pc(svc, 50), "service_p99_ms": pc(svc, 99), "pairs": n_pairs,
+           "budget_bytes": budget_bytes, "lanes": max_inflight, "admission": info}
     if fifo:
         out["fifo_plain"] = run_fifo(bx, t, a, b)
     return out

@@ -128,21 +128,38 @@ int bx_search_range(bx_ctx* ctx, uint64_t a, uint64_t b, uint32_t kinds, bx_pair
 int bx_search_batch(bx_ctx* ctx, const uint64_t* a, const uint64_t* b, size_t q, uint32_t kinds, bx_pair** out,
                     size_t* offsets);
 
-/* Serving (continuous batching).  bx_serve_start launches the library's
- * scheduler thread; requests are admitted while the device bytes of in-flight
- * work stay within budget_bytes and fewer than max_inflight batches run; work
- * of different batches overlaps on the device on separate streams.
- * bx_submit never blocks when wait == 0 (BX_EBUSY if the request can never fit
- * the budget).  bx_poll reports completion, bx_take hands over the pair list
- * (malloc'd) and releases the ticket.  Times are seconds on the library's
- * monotonic clock (bx_now).  Each of the max_inflight lanes is a context of
- * its own that takes the owner's search options (tile, seg_len, prune,
- * join, fp_bits, third_offset, group) as they are when serving starts. */
+/* Serving (continuous batching of range requests, each over an interval
+ * [start, start + length[ as in Algorithm 1, arriving over time).  bx_serve_start starts max_inflight lanes (1..8), each a context of
+ * its own with its own stream and workspace and one scheduler thread; a lane
+ * takes the owner's search options (tile, sieve, seg_len, prune, join,
+ * fp_bits, third_offset, group) as they are when serving starts.  A free lane
+ * admits queued requests in arrival order into one batch while the device
+ * bytes of all lanes' workspaces -- this lane's grown to what the batch's plan
+ * needs -- stay within budget_bytes (0 = half the owner's budget); a lane that
+ * finds no room lets its own idle workspace go.  Batches of different lanes
+ * overlap on the device.  bx_submit never blocks; it returns BX_EBUSY when
+ * the request alone needs more than the budget.  bx_poll reports completion,
+ * bx_take hands over the pair list (malloc'd) and releases the ticket.  Times
+ * are seconds on the library's monotonic clock (bx_now). */
 int bx_serve_start(bx_ctx* ctx, uint64_t budget_bytes, int max_inflight);
 int bx_serve_stop(bx_ctx* ctx);
 int bx_submit(bx_ctx* ctx, uint64_t a, uint64_t b, uint32_t kinds, uint64_t* ticket);
 int bx_poll(bx_ctx* ctx, uint64_t ticket, int* done);
 int bx_take(bx_ctx* ctx, uint64_t ticket, bx_pair** out, size_t* count, double* t_submit, double* t_done);
+
+/* Admission record of the running server. */
+typedef struct {
+  uint64_t budget_bytes;  /* the admission budget                                         */
+  uint64_t peak_bytes;    /* largest sum of the lanes' workspaces, reserved or held       */
+  uint64_t held_bytes;    /* that sum now                                                 */
+  uint64_t admitted;      /* requests admitted so far                                     */
+  uint64_t batches;       /* batches they ran in                                          */
+  uint32_t max_batch;     /* most requests in one batch                                   */
+  uint32_t lanes;
+  uint64_t memory_waits;  /* times a free lane found queued requests but no room          */
+  uint64_t releases;      /* times a lane let its workspace go to make room               */
+} bx_serve_info;
+int bx_serve_get_info(bx_ctx* ctx, bx_serve_info* out);
 double bx_now(void);
 
 /* Autotuner.  Times the batched search of the queries [a[i], b[i]) (q >= 1;

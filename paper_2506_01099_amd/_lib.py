@@ -17,7 +17,7 @@ _NAMES = {BX_EINVAL: "BX_EINVAL", BX_ERANGE: "BX_ERANGE", BX_ENOMEM: "BX_ENOMEM"
 EXPORTS = [
     "bx_create", "bx_destroy", "bx_set_stream", "bx_radical_segment", "bx_radical_segment_dev",
     "bx_radical_segment_dev_noalloc", "bx_benelux_search", "bx_search_range", "bx_search_batch", "bx_serve_start", "bx_serve_stop",
-    "bx_submit", "bx_poll", "bx_take", "bx_now", "bx_get_stats", "bx_set_option", "bx_free",
+    "bx_submit", "bx_poll", "bx_take", "bx_serve_get_info", "bx_now", "bx_get_stats", "bx_set_option", "bx_free",
     "bx_autotune", "bx_load_tuning",
     "bx_last_error", "benelux_search", "radical_segment",
 ]
@@ -32,6 +32,12 @@ class BxError(RuntimeError):
 class Pair(ctypes.Structure):
     _fields_ = [("m", ctypes.c_uint64), ("n", ctypes.c_uint64),
                 ("kind", ctypes.c_uint32), ("query", ctypes.c_uint32)]
+
+
+class ServeInfo(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64), ("held_bytes", ctypes.c_uint64),
+                ("admitted", ctypes.c_uint64), ("batches", ctypes.c_uint64), ("max_batch", ctypes.c_uint32),
+                ("lanes", ctypes.c_uint32), ("memory_waits", ctypes.c_uint64), ("releases", ctypes.c_uint64)]
 
 
 class Stats(ctypes.Structure):
@@ -84,6 +90,7 @@ def load():
         "bx_poll": ([vp, u64, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "bx_take": ([vp, u64, PP, ctypes.POINTER(sz), ctypes.POINTER(ctypes.c_double),
                      ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "bx_serve_get_info": ([vp, ctypes.POINTER(ServeInfo)], ctypes.c_int),
         "bx_now": ([], ctypes.c_double),
         "bx_autotune": ([vp, P64, P64, sz, ctypes.c_int, ctypes.c_char_p], ctypes.c_int),
         "bx_load_tuning": ([vp, ctypes.c_char_p], ctypes.c_int),

@@ -8,7 +8,7 @@ import ctypes
 
 import numpy as np
 
-from ._lib import Pair, Stats, check, load
+from ._lib import Pair, ServeInfo, Stats, check, load
 
 FIRST, SECOND, BOTH, THIRD = 1, 2, 3, 4  # THIRD: also rad(m+2) = rad(n+2) (kind 5)
 VALUE_LIMIT = 1 << 42
@@ -163,6 +163,12 @@ class Server:
         check(self._lib.bx_take(self.ctx._h, int(ticket), ctypes.byref(p), ctypes.byref(c), ctypes.byref(ts),
                                 ctypes.byref(td)))
         return _pairs_from(p, c.value), ts.value, td.value
+
+    def info(self):
+        """Admission record: budget, peak and current workspace bytes, batches, waits."""
+        v = ServeInfo()
+        check(self._lib.bx_serve_get_info(self.ctx._h, ctypes.byref(v)))
+        return {name: int(getattr(v, name)) for name, _ in ServeInfo._fields_}
 
     def now(self):
         return self._lib.bx_now()

@@ -21,6 +21,7 @@
 #include <thread>
 #include <vector>
 
+#include "bx_alg3.h"
 #include "bx_kernels.h"
 
 using namespace bx;
@@ -107,11 +108,13 @@ struct bx_ctx {
   uint32_t* d_primes = nullptr;
   PrimePow* d_pp = nullptr;
   DenseTab* d_dense[2] = {nullptr, nullptr};
-  DevBuf l1, l2, cnt1, cnt2, cand, out, flags, spill, queries, segpref, rad, acc;
+  DevBuf l1, l2, cnt1, cnt2, cand, out, flags, spill, queries, segpref, rad, acc, a3tab;
   int force_passes = 0, timing = 1, force_b1 = -1, force_b2 = -1, force_group = 0;
   int prune = 1;            // drop x that cannot be a pair member before the join
   int join_sort = 0;        // 1: the sort join per partition (ablation of the hash join)
   uint32_t third_off = 2;   // offset d of the third condition rad(m + d) = rad(n + d); 2 is Erdős's
+  int schedule = 0;         // 0: hash-partitioned passes, 1: Algorithm 3's chunk schedule (a baseline)
+  uint32_t a3_log2 = 27;    // Algorithm 3's chunk size s = 2^a3_log2 (a table of 4s slots)
   // Fingerprint bits kept: all 53 in use; tests keep the top 11 (the
   // partition bits) and a few low ones to make different sets collide.
   uint64_t fp_mask = (1ull << kFpBits) - 1;
@@ -303,6 +306,7 @@ uint32_t ceil_log2(double v) {
 
 uint64_t round_up(uint64_t v, uint64_t m) { return (v + m - 1) / m * m; }
 
+// Sparse hits per workgroup beyond the sieve's LDS list (worst case).
 uint32_t spill_cap_of(const bx_ctx* c) {
   return static_cast<uint32_t>(c->pp.size() - c->n_dense[0] + c->seg_len / 128 + 64);
 }
@@ -591,7 +595,14 @@ struct Job {
   uint32_t gmask = 0;
 };
 
-int prepare_job(bx_ctx* c, Segs& s, int batch, uint32_t kinds, hipStream_t st, Job* j) {
+// Bytes of every workspace buffer a job needs.
+struct JobBufs {
+  size_t l1, l2, cnt1, cnt2, cand, out, flags, acc, spill, queries, segpref;
+};
+
+// The plan and launch shapes of one search over `s` and the workspace it
+// needs; nothing is allocated.
+int plan_job(bx_ctx* c, Segs& s, int batch, uint32_t kinds, Job* j, JobBufs* nb) {
   int rc;
   j->s = &s;
   j->batch = batch;
@@ -614,16 +625,49 @@ int prepare_job(bx_ctx* c, Segs& s, int batch, uint32_t kinds, hipStream_t st, J
   j->part_grid = 8ull * std::min<uint64_t>(std::max(1, c->n_cu / 8), (chunks + per - 1) / per);
   if (j->part_grid > 0x7FFFFFFFull) return fail(BX_EINTERNAL, "partition grid too large");
   j->gmask = batch ? kGrpMask : 0u;
-  if ((rc = ensure(c, c->l1, j->n_regions * plan.cap1 * sizeof(Entry))) != BX_OK) return rc;
-  if ((rc = ensure(c, c->l2, j->ngsub * plan.cap2 * sizeof(Entry))) != BX_OK) return rc;
-  if ((rc = ensure(c, c->cnt1, j->n_regions * 4ull)) != BX_OK) return rc;
-  if ((rc = ensure(c, c->cnt2, j->ngsub * 4ull)) != BX_OK) return rc;
-  if ((rc = ensure(c, c->cand, kCandCap * sizeof(Cand))) != BX_OK) return rc;
-  if ((rc = ensure(c, c->out, kCandCap * sizeof(OutPair))) != BX_OK) return rc;
-  if ((rc = ensure(c, c->flags, kFlagCount * 4)) != BX_OK) return rc;
-  if ((rc = ensure(c, c->acc, kAccCount * sizeof(unsigned long long))) != BX_OK) return rc;
-  if ((rc = ensure(c, c->spill, static_cast<size_t>(j->sieve_grid) * spill_cap_of(c) * 8)) != BX_OK) return rc;
+  nb->l1 = j->n_regions * plan.cap1 * sizeof(Entry);
+  nb->l2 = j->ngsub * plan.cap2 * sizeof(Entry);
+  nb->cnt1 = j->n_regions * 4ull;
+  nb->cnt2 = j->ngsub * 4ull;
+  nb->cand = kCandCap * sizeof(Cand);
+  nb->out = kCandCap * sizeof(OutPair);
+  nb->flags = kFlagCount * 4;
+  nb->acc = kAccCount * sizeof(unsigned long long);
+  nb->spill = static_cast<size_t>(j->sieve_grid) * spill_cap_of(c) * 8;
+  nb->queries = s.q.size() * sizeof(Query);
+  nb->segpref = s.prefix.size() * sizeof(uint64_t);
+  return BX_OK;
+}
+
+// What the workspace holds once a job with buffers nb has run: each buffer
+// keeps its size or grows to the job's (from zero when `released`).
+uint64_t bytes_after(const bx_ctx* c, const JobBufs& nb, bool released) {
+  const std::pair<const DevBuf*, size_t> v[] = {{&c->l1, nb.l1},       {&c->l2, nb.l2},
+                                                {&c->cnt1, nb.cnt1},   {&c->cnt2, nb.cnt2},
+                                                {&c->cand, nb.cand},   {&c->out, nb.out},
+                                                {&c->flags, nb.flags}, {&c->acc, nb.acc},
+                                                {&c->spill, nb.spill}, {&c->queries, nb.queries},
+                                                {&c->segpref, nb.segpref}, {&c->rad, 0}};
+  uint64_t t = 0;
+  for (const auto& e : v) t += std::max<uint64_t>(released ? 0 : e.first->bytes, std::max<size_t>(e.second, 256));
+  return t;
+}
+
+int prepare_job(bx_ctx* c, Segs& s, int batch, uint32_t kinds, hipStream_t st, Job* j) {
+  int rc;
+  JobBufs nb;
+  if ((rc = plan_job(c, s, batch, kinds, j, &nb)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->l1, nb.l1)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->l2, nb.l2)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->cnt1, nb.cnt1)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->cnt2, nb.cnt2)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->cand, nb.cand)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->out, nb.out)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->flags, nb.flags)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->acc, nb.acc)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->spill, nb.spill)) != BX_OK) return rc;
   if ((rc = upload_segs(c, s, st)) != BX_OK) return rc;
+  const Plan& plan = j->plan;
   c->stats.b1_bits = plan.b1bits;
   c->stats.b2_bits = plan.b2bits;
   c->stats.seg_len = c->seg_len;
@@ -822,7 +866,6 @@ int run_passes_checked(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* 
 int run_passes_graph(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* result, int* redo) {
   int rc;
   *redo = 0;
-  // Every launch shape and every buffer address the graph's kernels use.
   char key[1024];
   // Every launch shape, every option baked into a kernel argument or choice,
   // and every buffer address the graph's kernels use.
@@ -911,7 +954,7 @@ int to_pairs(const std::vector<OutPair>& v, bx_pair** out, size_t* count) {
   return BX_OK;
 }
 
-int radicals_into(bx_ctx* c, uint64_t lo, uint64_t hi, uint64_t* dev_out, hipStream_t st) {
+int radicals_into(bx_ctx* c, uint64_t lo, uint64_t hi, uint64_t* dev_out, hipStream_t st, bool clear_flags = true) {
   Segs s;
   s.q.push_back(Query{lo, hi});
   make_segs(c, &s);
@@ -921,7 +964,7 @@ int radicals_into(bx_ctx* c, uint64_t lo, uint64_t hi, uint64_t* dev_out, hipStr
   if ((rc = ensure(c, c->flags, kFlagCount * 4)) != BX_OK) return rc;
   const uint32_t grid = static_cast<uint32_t>(std::min<uint64_t>(s.n_segs, 2ull * sieve_wg_per_cu(c) * c->n_cu));
   if ((rc = ensure(c, c->spill, static_cast<size_t>(grid) * spill_cap_of(c) * 8)) != BX_OK) return rc;
-  if ((rc = fill_u32(c, c->flags.p, kFlagCount, 0, st)) != BX_OK) return rc;
+  if (clear_flags && (rc = fill_u32(c, c->flags.p, kFlagCount, 0, st)) != BX_OK) return rc;
   SieveParams P = base_sieve_params(c, s);
   P.rad_out = dev_out;
   P.rad_lo = lo;
@@ -932,6 +975,79 @@ int radicals_into(bx_ctx* c, uint64_t lo, uint64_t hi, uint64_t* dev_out, hipStr
   }
   BX_HIP(hipGetLastError());
   return BX_OK;
+}
+
+// Algorithm 3's schedule over [a, b): chunks C_i of s values overlapping by
+// one; C_i's entries go into a table of 4s slots (pairs inside C_i found on
+// insertion), then every earlier chunk is sieved again and probes the table.
+// The candidates are verified as in the passes.  Work grows with the square
+// of the range: it is the paper's design, kept as a baseline.
+int run_alg3(bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds, std::vector<OutPair>* result) {
+  hipStream_t st = c->stream;
+  result->clear();
+  int rc;
+  if ((rc = order_after_last(c, st)) != BX_OK) return rc;
+  if ((rc = mark_done(c, st)) != BX_OK) return rc;
+  const uint64_t s = 1ull << c->a3_log2, step = s - 1;
+  const uint64_t n_chunks = (b - a + step - 1) / step;
+  const uint64_t slots = 4 * s;
+  if ((rc = ensure(c, c->a3tab, slots * sizeof(uint64_t))) != BX_OK) return rc;
+  if ((rc = ensure(c, c->rad, (s + 1) * sizeof(uint64_t))) != BX_OK) return rc;
+  if ((rc = ensure(c, c->cand, kCandCap * sizeof(Cand))) != BX_OK) return rc;
+  if ((rc = ensure(c, c->out, kCandCap * sizeof(OutPair))) != BX_OK) return rc;
+  if ((rc = ensure(c, c->flags, kFlagCount * 4)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->acc, kAccCount * sizeof(unsigned long long))) != BX_OK) return rc;
+  if ((rc = fill_u32(c, c->flags.p, kFlagCount, 0, st)) != BX_OK) return rc;
+  if ((rc = fill_u32(c, c->acc.p, 2 * kAccCount, 0, st)) != BX_OK) return rc;
+  uint64_t* rad = static_cast<uint64_t*>(c->rad.p);
+  A3Params P;
+  P.rad = rad;
+  P.table = static_cast<uint64_t*>(c->a3tab.p);
+  P.tmask = slots - 1;
+  P.cand = static_cast<Cand*>(c->cand.p);
+  P.cand_cap = kCandCap;
+  P.flags = static_cast<uint32_t*>(c->flags.p);
+  auto grid_for = [&](uint64_t n) { return static_cast<uint32_t>(std::min<uint64_t>((n + 255) / 256, 8192)); };
+  for (uint64_t i = 0; i < n_chunks; ++i) {
+    const uint64_t ci = a + i * step, cnt_i = std::min(step, b - ci);  // entries n in [ci, ci + cnt_i)
+    hipLaunchKernelGGL(k_fill_u64, dim3(4096), dim3(256), 0, st, P.table, slots, kA3Empty);
+    BX_HIP(hipGetLastError());
+    if ((rc = radicals_into(c, ci, ci + cnt_i + 1, rad, st, false)) != BX_OK) return rc;
+    P.c0 = ci;
+    P.count = static_cast<uint32_t>(cnt_i);
+    P.n0 = ci;
+    {
+      LaunchTimer t(c, K_JOIN, st);
+      hipLaunchKernelGGL(k_a3_insert, dim3(grid_for(cnt_i)), dim3(256), 0, st, P);
+    }
+    BX_HIP(hipGetLastError());
+    for (uint64_t j = 0; j < i; ++j) {
+      const uint64_t cj = a + j * step;  // a full chunk: entries m in [cj, cj + step)
+      if ((rc = radicals_into(c, cj, cj + step + 1, rad, st, false)) != BX_OK) return rc;
+      P.c0 = cj;
+      P.count = static_cast<uint32_t>(step);
+      P.n0 = ci;
+      {
+        LaunchTimer t(c, K_JOIN, st);
+        hipLaunchKernelGGL(k_a3_probe, dim3(grid_for(step)), dim3(256), 0, st, P);
+      }
+      BX_HIP(hipGetLastError());
+    }
+    c->stats.passes++;
+  }
+  c->stats.integers = b - a;
+  uint32_t fl[kFlagCount];
+  if ((rc = read_flags(c, fl, st)) != BX_OK) return rc;
+  if (fl[kFlagSpillOverflow]) return fail(BX_EINTERNAL, "sparse-hit overflow in the radical sieve");
+  if (fl[kFlagCand] > kCandCap) return fail(BX_EINTERNAL, "candidate buffer overflow");
+  if (fl[kFlagCand] > 0) {
+    Job j;
+    j.batch = 0;
+    j.kinds = kinds;
+    if ((rc = enqueue_verify(c, j, std::min<uint32_t>(fl[kFlagCand], kVerifyGrid), st)) != BX_OK) return rc;
+    if ((rc = read_flags(c, fl, st)) != BX_OK) return rc;
+  }
+  return collect_pairs(c, fl, st, result);
 }
 
 // Scratch of bx_radical_segment_dev_noalloc: the counter words, the one-query
@@ -992,9 +1108,9 @@ int default_ctx(bx_ctx** out) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Serving: a scheduler thread forms batches of admitted requests and runs each
-// batch on its own context (own stream, own workspace), so the work of
-// different batches overlaps on the device.
+// Serving: one scheduler thread per lane forms batches of admitted requests
+// and runs each batch on the lane's own context (own stream, own workspace),
+// so the work of different batches overlaps on the device.
 struct bx_ctx::Server {
   struct Req {
     uint64_t a, b;
@@ -1012,8 +1128,12 @@ struct bx_ctx::Server {
   std::deque<uint64_t> queue;
   std::map<uint64_t, std::unique_ptr<Req>> reqs;
   uint64_t next_ticket = 1;
-  uint64_t inflight_bytes = 0;
-  int inflight = 0;
+  // Device bytes of each lane's workspace: reserved for the batch it runs
+  // (what the batch's plan grows it to) or held between batches.  Their sum
+  // never exceeds the budget.
+  std::vector<uint64_t> held;
+  uint64_t peak = 0, admitted = 0, batches = 0, mem_waits = 0, releases = 0;
+  uint32_t max_batch = 0;
   bool stop = false;
   std::vector<std::thread> workers;
   std::vector<bx_ctx*> lanes;
@@ -1021,51 +1141,129 @@ struct bx_ctx::Server {
 
 namespace {
 
-uint64_t request_bytes(uint64_t a, uint64_t b) {
-  const uint64_t L = b > a ? b - a : 0;
-  return L * 2 * sizeof(Entry);  // entries in both partition buffers
+uint64_t workspace_bytes(const bx_ctx* c) {
+  uint64_t t = 0;
+  for (const DevBuf* b : {&c->l1, &c->l2, &c->cnt1, &c->cnt2, &c->cand, &c->out, &c->flags, &c->spill, &c->queries,
+                          &c->segpref, &c->rad, &c->acc})
+    t += b->bytes;
+  return t;
+}
+
+void release_workspace(bx_ctx* c) {
+  std::lock_guard<std::mutex> lk(c->mu);
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (DevBuf* b : {&c->l1, &c->l2, &c->cnt1, &c->cnt2, &c->cand, &c->out, &c->flags, &c->spill, &c->queries,
+                    &c->segpref, &c->rad, &c->acc})
+    free_buf(*b);
+  if (c->graph_exec) {
+    (void)hipGraphExecDestroy(c->graph_exec);
+    c->graph_exec = nullptr;
+  }
+}
+
+// The workspace the lane context c would hold after running the batch of
+// queries q (released first or not), or the bare need (`released` = true).
+// *passes receives the number of hash passes its plan takes.
+int batch_bytes(bx_ctx* c, const std::vector<Query>& q, bool released, uint64_t* bytes, uint32_t* passes = nullptr) {
+  Segs s;
+  s.q = q;
+  make_segs(c, &s);
+  *bytes = 0;
+  if (passes) *passes = 1;
+  if (s.n_segs == 0) return BX_OK;
+  Job j;
+  JobBufs nb;
+  const int rc = plan_job(c, s, 1, BX_BOTH, &j, &nb);
+  if (rc != BX_OK) return rc;
+  *bytes = bytes_after(c, nb, released);
+  if (passes) *passes = j.plan.passes;
+  return BX_OK;
 }
 
 void serve_worker(bx_ctx::Server* S, int lane) {
   bx_ctx* c = S->lanes[lane];
   for (;;) {
     std::vector<uint64_t> batch;
-    uint64_t bytes = 0;
+    bool release_first = false;
     {
       std::unique_lock<std::mutex> lk(S->mu);
       S->cv.wait(lk, [&] { return S->stop || !S->queue.empty(); });
       if (S->stop && S->queue.empty()) return;
-      // Admit queued requests in arrival order while the in-flight bytes stay
-      // within the budget (a lone request is always admitted).
+      uint64_t others = 0;
+      for (int l = 0; l < S->max_inflight; ++l)
+        if (l != lane) others += S->held[l];
+      // Admit queued requests in arrival order while the lanes' workspaces,
+      // this one grown to what the batch's plan needs, stay within the budget,
+      // and while the batch needs no more hash passes than its first request
+      // (a batch that re-sieves more often is better split).
+      std::vector<Query> q;
+      uint64_t reserve = 0;
+      uint32_t p_first = 1;
       while (!S->queue.empty() && batch.size() < kMaxQueries) {
-        const uint64_t t = S->queue.front();
-        auto& r = *S->reqs[t];
-        const uint64_t rb = request_bytes(r.a, r.b);
-        if (!batch.empty() && S->inflight_bytes + rb > S->budget) break;
-        if (batch.empty() && S->inflight_bytes > 0 && S->inflight_bytes + rb > S->budget) break;
+        const auto& r = *S->reqs[S->queue.front()];
+        q.push_back(Query{r.a, r.b});
+        uint64_t grown = 0, bare = 0;
+        uint32_t passes = 1;
+        if (batch_bytes(c, q, false, &grown, &passes) != BX_OK) grown = UINT64_MAX;
+        if (batch.empty()) p_first = passes;
+        if (!batch.empty() && passes > p_first) {
+          q.pop_back();
+          break;
+        }
+        if (others + grown <= S->budget) {
+          reserve = grown;
+        } else if (batch.empty() && batch_bytes(c, q, true, &bare) == BX_OK && others + bare <= S->budget) {
+          reserve = bare;  // fits once this lane's own workspace is released
+          release_first = true;
+        } else {
+          q.pop_back();
+          break;
+        }
+        batch.push_back(S->queue.front());
         S->queue.pop_front();
-        S->inflight_bytes += rb;
-        bytes += rb;
-        batch.push_back(t);
+        if (release_first) break;
       }
       if (batch.empty()) {
-        S->cv.wait_for(lk, std::chrono::milliseconds(1));
+        // No room: the other lanes hold the budget.  An idle lane lets its
+        // workspace go, so that busy lanes finishing their batches (which
+        // then find the queue waiting) eventually leave room.
+        S->mem_waits++;
+        if (S->held[lane] > 0) {
+          S->held[lane] = 0;
+          lk.unlock();
+          release_workspace(c);
+          lk.lock();
+          S->releases++;
+          S->cv.notify_all();
+        } else {
+          S->cv.wait_for(lk, std::chrono::milliseconds(1));
+        }
         continue;
       }
-      S->inflight++;
+      S->held[lane] = reserve;
+      uint64_t total = 0;
+      for (uint64_t h : S->held) total += h;
+      S->peak = std::max(S->peak, total);
+      S->admitted += batch.size();
+      S->batches++;
+      S->max_batch = std::max<uint32_t>(S->max_batch, static_cast<uint32_t>(batch.size()));
+      if (release_first) S->releases++;
     }
+    if (release_first) release_workspace(c);
     Segs s;
     std::vector<uint32_t> kinds;
     {
       std::lock_guard<std::mutex> lk(S->mu);
       for (uint64_t t : batch) {
         auto& r = *S->reqs[t];
-        s.q.push_back(Query{std::max<uint64_t>(r.a, 1), r.b});
+        s.q.push_back(Query{r.a, r.b});
         kinds.push_back(r.kinds);
       }
     }
     std::vector<OutPair> res;
     int rc;
+    uint64_t after = 0;
     {
       std::lock_guard<std::mutex> lk(c->mu);
       reset_stats(c);
@@ -1074,6 +1272,7 @@ void serve_worker(bx_ctx::Server* S, int lane) {
       rc = run_search(c, s, 1, kall, &res, c->graph_batch != 0);
       (void)hipStreamSynchronize(c->stream);
       collect_timings(c);
+      after = workspace_bytes(c);
     }
     const double t_done = now_s();
     {
@@ -1090,8 +1289,8 @@ void serve_worker(bx_ctx::Server* S, int lane) {
         const bool three = (r.kinds & BX_THIRD) && (p.kind & BX_THIRD);
         if ((r.kinds & base) || three) r.pairs.push_back(OutPair{p.m, p.n, three ? p.kind : base, 0});
       }
-      S->inflight_bytes -= bytes;
-      S->inflight--;
+      // What the lane holds now (at most what was reserved for the batch).
+      S->held[lane] = std::min(after, S->held[lane]);
     }
     S->cv.notify_all();
   }
@@ -1138,7 +1337,7 @@ void bx_destroy(bx_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (DevBuf* b : {&c->l1, &c->l2, &c->cnt1, &c->cnt2, &c->cand, &c->out, &c->flags, &c->spill, &c->queries,
-                    &c->segpref, &c->rad, &c->acc})
+                    &c->segpref, &c->rad, &c->acc, &c->a3tab})
     free_buf(*b);
   if (c->d_primes) (void)hipFree(c->d_primes);
   if (c->d_pp) (void)hipFree(c->d_pp);
@@ -1176,6 +1375,13 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
   } else if (n == "tile") {
     if (v != 0 && v != kTileSmall && v != kTileLarge) return fail(BX_EINVAL, "tile must be 0, 2048 or 8192");
     c->tile = v == 0 ? kTileDefault : static_cast<int>(v);
+  } else if (n == "schedule") {
+    if (v != 0 && v != 1) return fail(BX_EINVAL, "schedule must be 0 (hash-partitioned passes) or 1 (Algorithm 3)");
+    c->schedule = static_cast<int>(v);
+  } else if (n == "a3_chunk_log2") {
+    if (v == 0) v = 27;
+    if (v < 10 || v > 27) return fail(BX_EINVAL, "a3_chunk_log2 must be in [10, 27]");
+    c->a3_log2 = static_cast<uint32_t>(v);
   } else if (n == "graph") {
     c->graph_batch = v != 0;
   } else if (n == "prune") {
@@ -1347,7 +1553,7 @@ int bx_search_range(bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds, bx_pair**
   Segs s;
   s.q.push_back(Query{a, b});
   std::vector<OutPair> res;
-  rc = run_search(c, s, 0, kinds, &res, false);
+  rc = c->schedule == 1 ? run_alg3(c, a, b, kinds, &res) : run_search(c, s, 0, kinds, &res, false);
   (void)hipStreamSynchronize(c->stream);
   collect_timings(c);
   c->stats.total_ms = (now_s() - t0) * 1e3;
@@ -1367,6 +1573,7 @@ int bx_search_batch(bx_ctx* c, const uint64_t* a, const uint64_t* b, size_t q, u
   if (kinds < 1 || kinds > 7) return fail(BX_EINVAL, "kinds must be a mask in 1..7");
   if (q > kMaxQueries) return fail(BX_EINVAL, "at most 32768 queries per batch");
   std::lock_guard<std::mutex> lk(c->mu);
+  if (c->schedule != 0) return fail(BX_EINVAL, "batched calls run the hash-partitioned passes only (schedule 0)");
   const double t0 = now_s();
   reset_stats(c);
   Segs s;
@@ -1407,10 +1614,11 @@ int bx_serve_start(bx_ctx* c, uint64_t budget_bytes, int max_inflight) {
   S->owner = c;
   S->budget = budget_bytes ? budget_bytes : c->budget / 2;
   S->max_inflight = max_inflight;
+  S->held.assign(max_inflight, 0);
   for (int i = 0; i < max_inflight; ++i) {
     bx_ctx* lane = nullptr;
-    const uint64_t lane_budget = S->budget / max_inflight + (1ull << 30);
-    int rc = bx_create(&lane, c->device, c->hi_max, lane_budget);
+    // A lane may plan with the whole budget; admission keeps the sum in it.
+    int rc = bx_create(&lane, c->device, c->hi_max, S->budget);
     if (rc != BX_OK) {
       for (bx_ctx* l : S->lanes) bx_destroy(l);
       return rc;
@@ -1458,7 +1666,17 @@ int bx_submit(bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds, uint64_t* ticke
     if (rc != BX_OK) return rc;
   }
   auto* S = c->server.get();
-  if (request_bytes(a, b) > S->budget) return fail(BX_EBUSY, "request can never fit the serving budget");
+  if (b > a + 1) {
+    // The workspace this request needs on a lane by itself (the lanes' plans
+    // depend only on options fixed when serving started).
+    uint64_t need = 0;
+    const int rc = batch_bytes(S->lanes[0], {Query{a, b}}, true, &need);
+    if (rc == BX_ENOMEM) return fail(BX_EBUSY, "request cannot be planned within the serving budget: " + g_err);
+    if (rc != BX_OK) return rc;
+    if (need > S->budget)
+      return fail(BX_EBUSY, "request needs " + std::to_string(need) + " device bytes, more than the serving budget " +
+                                std::to_string(S->budget));
+  }
   {
     std::lock_guard<std::mutex> lk(S->mu);
     const uint64_t t = S->next_ticket++;
@@ -1503,6 +1721,25 @@ int bx_take(bx_ctx* c, uint64_t ticket, bx_pair** out, size_t* count, double* t_
   if (t_done) *t_done = r->t_done;
   if (r->rc != BX_OK) return fail(r->rc, "request failed");
   return to_pairs(r->pairs, out, count);
+}
+
+int bx_serve_get_info(bx_ctx* c, bx_serve_info* out) {
+  if (!c || !out) return fail(BX_EINVAL, "NULL argument");
+  if (!c->server) return fail(BX_EINVAL, "server not started");
+  auto* S = c->server.get();
+  std::lock_guard<std::mutex> lk(S->mu);
+  bx_serve_info v{};
+  v.budget_bytes = S->budget;
+  v.peak_bytes = S->peak;
+  for (uint64_t h : S->held) v.held_bytes += h;
+  v.admitted = S->admitted;
+  v.batches = S->batches;
+  v.max_batch = S->max_batch;
+  v.lanes = static_cast<uint32_t>(S->max_inflight);
+  v.memory_waits = S->mem_waits;
+  v.releases = S->releases;
+  *out = v;
+  return BX_OK;
 }
 
 int bx_autotune(bx_ctx* c, const uint64_t* a, const uint64_t* b, size_t q, int reps, const char* path) {

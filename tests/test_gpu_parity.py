@@ -189,6 +189,44 @@ def test_sort_join_matches_oracle(ctx, N):
     assert got == oracle.search(N)
 
 
+@pytest.mark.parametrize("N,log2s", [(1 << 20, 14), (1 << 24, 18), ((1 << 20) + 12345, 16)])
+def test_paper_schedule_matches_oracle(ctx, N, log2s):
+    """Algorithm 3's chunk schedule (chunks of s values overlapping by one, a table of
+    4s slots per chunk, every earlier chunk sieved again and probed) finds the same
+    pairs as the oracle, including pairs inside one chunk and across chunks."""
+    ctx.set_option("schedule", 1)
+    ctx.set_option("a3_chunk_log2", log2s)
+    try:
+        got = ctx.search(N)
+        st = ctx.stats()
+        rng = ctx.search_range(70, N // 3, 3)
+        first = ctx.search(N, 1)
+    finally:
+        ctx.set_option("schedule", 0)
+        ctx.set_option("a3_chunk_log2", 0)
+    assert got == oracle.search(N)
+    assert rng == oracle.search_range(70, N // 3, 3)
+    assert first == [p for p in got if p[2] == 1]
+    assert st["passes"] == -(-N // ((1 << log2s) - 1))  # one pass per chunk
+    assert st["candidates"] >= len(got)
+
+
+def test_paper_schedule_2_32_theorem1(ctx):
+    """The paper's own configuration (chunks of 2^27, tables of 2^29 slots) up to 2^32."""
+    say("Algorithm 3 schedule up to 2^32")
+    ctx.set_option("schedule", 1)
+    try:
+        got = ctx.search(1 << 32)
+        st = ctx.stats()
+        with pytest.raises(Exception):
+            ctx.search_batch(np.array([1], dtype=np.uint64), np.array([100], dtype=np.uint64))
+    finally:
+        ctx.set_option("schedule", 0)
+    assert got == theorem1_pairs(1 << 32)
+    assert st["passes"] == -(-(1 << 32) // ((1 << 27) - 1))  # 33 chunks of 2^27 - 1 new values
+    say(f"  {st['total_ms']:.0f} ms")
+
+
 def test_sort_join_chunks_collisions_and_batch(ctx):
     """Partitions of several LDS chunks (one first- and one second-level bit), colliding
     fingerprints and a batch, all through the sort join."""
@@ -582,6 +620,56 @@ def test_served_alone_equals_in_mix(ctx):
         pairs, ts, td = results[t]
         assert pairs == want
         assert td >= ts
+
+
+def test_served_budget_binds(ctx):
+    """A budget that holds the workspace of about two of these requests: admission holds
+    the others back, the lanes' workspaces never sum past the budget, and every result
+    equals the request run alone."""
+    import time
+
+    from paper_2506_01099_amd import Server
+
+    base = 1 << 40
+    reqs = [(base + i * (1 << 25), base + (i + 1) * (1 << 25)) for i in range(6)]
+    reqs += [(1, 1 << 22), (70, 1300), (1 << 30, (1 << 30) + (1 << 24))]
+    alone = [ctx.search_range(a, b) for a, b in reqs]
+    budget = 400 << 20
+    srv = Server(ctx, budget_bytes=budget, max_inflight=3)
+    try:
+        tickets = [srv.submit(a, b) for a, b in reqs]
+        deadline = time.time() + 120
+        results = {}
+        while len(results) < len(tickets) and time.time() < deadline:
+            for t in tickets:
+                if t not in results and srv.poll(t):
+                    results[t] = srv.take(t)[0]
+            time.sleep(0.001)
+        info = srv.info()
+    finally:
+        srv.stop()
+    say(f"served under a {budget >> 20} MiB budget: {info}")
+    assert len(results) == len(tickets)
+    for t, want in zip(tickets, alone):
+        assert results[t] == want
+    assert info["budget_bytes"] == budget and info["admitted"] == len(reqs)
+    assert 0 < info["peak_bytes"] <= budget
+    assert info["memory_waits"] > 0 and info["batches"] >= 2
+
+
+def test_served_request_beyond_budget_is_refused(ctx):
+    """A request whose workspace cannot be planned within the budget (even split into
+    passes) is refused at submission, without blocking."""
+    from paper_2506_01099_amd import BxError, Server
+
+    srv = Server(ctx, budget_bytes=96 << 20, max_inflight=1)
+    try:
+        with pytest.raises(BxError) as ei:
+            srv.submit(1 << 40, (1 << 40) + (1 << 24))
+        assert ei.value.code == -5  # BX_EBUSY
+        assert srv.info()["admitted"] == 0
+    finally:
+        srv.stop()
 
 
 def test_served_kinds_and_lane_options(ctx):
