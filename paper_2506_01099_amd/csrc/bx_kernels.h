@@ -114,15 +114,27 @@ struct SieveShSel<T, BLOCK, MODE_KEYS> {
 // bucket b: shared by all workgroups (global, one atomic per non-empty bucket)
 // or, with PRIVATE, owned by this workgroup (no atomics).  dst(b, k) stores the
 // k-th entry of the bucket (k < cap).
-template <int BLOCK, int NB, bool PRIVATE, typename Bucket, typename Dst, typename Mid>
+template <int BLOCK, int NB, int NMAX, bool PRIVATE, typename Bucket, typename Dst, typename Mid>
 __device__ void scatter_runs(uint32_t n, uint32_t nb, const Entry* ent, Bucket sb, uint16_t* perm,
                              uint32_t* cnt, uint32_t* gofs, uint32_t* wsum, uint32_t* gcur, uint64_t cap,
                              uint32_t* flag, Dst dst, Mid mid) {
   constexpr int BINS = (NB + BLOCK - 1) / BLOCK;
+  // n <= NMAX: each thread takes the U entries tid + u * BLOCK, and every
+  // step issues the LDS reads and atomics of all of them before it waits on
+  // any (a thread past n reads entry 0 and leaves it alone).
+  constexpr int U = (NMAX + BLOCK - 1) / BLOCK;
   const int tid = threadIdx.x;
   for (uint32_t b = tid; b < nb; b += BLOCK) cnt[b] = 0;
   __syncthreads();
-  for (uint32_t i = tid; i < n; i += BLOCK) atomicAdd(&cnt[sb(i)], 1u);
+  uint32_t bk[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint32_t i = tid + u * BLOCK;
+    bk[u] = sb(i < n ? i : 0u);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (tid + u * BLOCK < n) atomicAdd(&cnt[bk[u]], 1u);
   __syncthreads();
   uint32_t loc[BINS];
   uint32_t sum = 0;
@@ -152,30 +164,40 @@ __device__ void scatter_runs(uint32_t n, uint32_t nb, const Entry* ent, Bucket s
   }
   __syncthreads();
   mid();  // the global cursors are taken: work that may overlap the scatter
-  for (uint32_t i = tid; i < n; i += BLOCK) perm[atomicAdd(&cnt[sb(i)], 1u)] = static_cast<uint16_t>(i);
+  uint32_t slot[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    slot[u] = tid + u * BLOCK < n ? atomicAdd(&cnt[bk[u]], 1u) : 0u;
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (tid + u * BLOCK < n) perm[slot[u]] = static_cast<uint16_t>(tid + u * BLOCK);
   __syncthreads();
-  for (uint32_t j = tid; j < n; j += BLOCK) {
-    const uint32_t i = perm[j];
-    const uint32_t b = sb(i);
-    const uint32_t k = gofs[b] + j;
-    if (k < cap)
-      dst(b, k, ent[i]);
-    else
-      atomicOr(flag, 1u);
+  uint32_t pi[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint32_t j = tid + u * BLOCK;
+    pi[u] = perm[j < n ? j : 0u];
+  }
+  uint32_t pb[U];
+  Entry pe[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    pb[u] = sb(pi[u]);
+    pe[u] = ent[pi[u]];
+  }
+  uint32_t pk[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) pk[u] = gofs[pb[u]] + tid + u * BLOCK;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (tid + u * BLOCK < n) {
+      if (pk[u] < cap)
+        dst(pb[u], pk[u], pe[u]);
+      else
+        atomicOr(flag, 1u);
+    }
   }
   __syncthreads();
-}
-
-// A kept integer waits in its stage slot as (rad(x), rad(x + 1)), both below
-// 2^42 and so within the slot's 96 bits, with i = x - x0, its index in the
-// tile, in the slot's bucket word; the next tile's division phase (or a flush)
-// turns it into an entry with every thread of the workgroup at work.
-__device__ __forceinline__ Entry pack_pending(uint64_t a, uint64_t b) {
-  Entry e;
-  e.w0 = static_cast<uint32_t>(a);
-  e.w1 = static_cast<uint32_t>(a >> 32) | (static_cast<uint32_t>(b) << 10);
-  e.w2 = static_cast<uint32_t>(b >> 22);
-  return e;
 }
 
 // Entry of the kept integer x = x0 + i with rad(x) = a and rad(x + 1) = b;
@@ -189,20 +211,11 @@ __device__ __forceinline__ Entry kept_entry(const SieveParams& P, uint64_t a, ui
   return make_entry(pos43, h >> 11);
 }
 
-// Turns the waiting slots [lo, hi) of one tile (first value x0, query start
-// qa, query id grp) into entries and their buckets, one slot per thread.
-template <int T, int BLOCK>
-__device__ void build_pending(SieveShKeys<T, BLOCK>& sh, const SieveParams& P, uint32_t lo, uint32_t hi, uint64_t x0,
-                              uint64_t qa, uint32_t grp) {
-  for (uint32_t s = lo + threadIdx.x; s < hi; s += BLOCK) {
-    const Entry r = sh.stage[s];
-    const uint64_t a = r.w0 | (static_cast<uint64_t>(r.w1 & 0x3FFu) << 32);
-    const uint64_t b = (r.w1 >> 10) | (static_cast<uint64_t>(r.w2) << 22);
-    const uint32_t i = sh.sb[s];
-    uint32_t bk;
-    sh.stage[s] = kept_entry(P, a, b, x0 + i, qa, grp, &bk);
-    sh.sb[s] = static_cast<uint16_t>(bk);
-  }
+// Orders the LDS accesses of one wave (its lanes share stage slots).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Lane mask of the wave's integers x (one per lane, rad(x) = r0 and
@@ -244,11 +257,10 @@ __device__ void flush_stage(SieveShKeys<T, BLOCK>& sh, const SieveParams& P) {
   Entry* l1 = P.l1 + static_cast<uint64_t>(blockIdx.x) * cap1;
   const uint16_t* sb = sh.sb;
   auto* fs = sh.flush_scratch();
-  scatter_runs<BLOCK, kB1Max, true>(n, P.b1mask + 1, sh.stage, [=](uint32_t i) -> uint32_t { return sb[i]; }, fs->perm,
-                                    fs->cnt, fs->gofs, sh.wsum, sh.lcur, cap1,
-                                    &P.flags[kFlagL1Overflow],
-                                    [=](uint32_t b, uint32_t k, const Entry& e) { l1[b * W * cap1 + k] = e; },
-                                    [] {});
+  scatter_runs<BLOCK, kB1Max, SieveShKeys<T, BLOCK>::kStage, true>(
+      n, P.b1mask + 1, sh.stage, [=](uint32_t i) -> uint32_t { return sb[i]; }, fs->perm, fs->cnt, fs->gofs, sh.wsum,
+      sh.lcur, cap1, &P.flags[kFlagL1Overflow],
+      [=](uint32_t b, uint32_t k, const Entry& e) { l1[b * W * cap1 + k] = e; }, [] {});
   if (threadIdx.x == 0) sh.stage_n = 0;
   __syncthreads();
 }
@@ -297,11 +309,6 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
   __syncthreads();
   uint64_t* spill = P.spill + static_cast<uint64_t>(blockIdx.x) * P.spill_cap;
 
-  // The previous tile's kept integers wait in stage slots [plo, ...); that
-  // tile started at px0 in the query starting at pqa with id pgrp.
-  uint32_t plo = 0;
-  uint64_t px0 = 0, pqa = 0;
-  uint32_t pgrp = 0;
   for (uint64_t s = blockIdx.x; s < P.n_segs; s += gridDim.x) {
     // Segment s -> query q and its x-interval [start, start + len).
     uint32_t lo = 0, hi = P.n_queries;
@@ -362,36 +369,41 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
     // multiples in [start, V] are listed once per segment (Algorithm 1's
     // first-multiple offset, start mod q).
     const uint32_t n_act = sh.n_act;
-    for (uint32_t idx = P.n_dense + tid; idx < n_act; idx += BLOCK) {
-      const PrimePow pw = P.pp[idx];
-      const uint64_t r = mod_fp64(start, pw.q, pw.invq);
-      for (uint64_t j = r ? pw.q - r : 0; j <= len; j += pw.q) {
-        const uint32_t k = atomicAdd(&sh.hit_n, 1u);
-        const uint64_t e = (j << 32) | pw.p;
-        if (k < kHitCap)
-          sh.hits[k] = e;
-        else if (k - kHitCap < P.spill_cap)
-          spill[k - kHitCap] = e;
-        else
-          atomicOr(&P.flags[kFlagSpillOverflow], 1u);
+    // Four powers per thread and round, their table words loaded together
+    // (a thread past the end loads the last active power and ignores it).
+    constexpr int kA = 4;
+    for (uint32_t idx0 = P.n_dense + tid; idx0 < n_act; idx0 += kA * BLOCK) {
+      PrimePow pw[kA];
+#pragma unroll
+      for (int u = 0; u < kA; ++u) {
+        const uint32_t idx = idx0 + u * BLOCK;
+        pw[u] = P.pp[idx < n_act ? idx : n_act - 1];
+      }
+#pragma unroll
+      for (int u = 0; u < kA; ++u) {
+        if (idx0 + u * BLOCK >= n_act) break;
+        const uint64_t r = mod_fp64(start, pw[u].q, pw[u].invq);
+        for (uint64_t j = r ? pw[u].q - r : 0; j <= len; j += pw[u].q) {
+          const uint32_t k = atomicAdd(&sh.hit_n, 1u);
+          const uint64_t e = (j << 32) | pw[u].p;
+          if (k < kHitCap)
+            sh.hits[k] = e;
+          else if (k - kHitCap < P.spill_cap)
+            spill[k - kHitCap] = e;
+          else
+            atomicOr(&P.flags[kFlagSpillOverflow], 1u);
+        }
       }
     }
     __syncthreads();
     const uint32_t nh = min(sh.hit_n, kHitCap + P.spill_cap);
 
     for (uint32_t base = 0; base < len; base += T) {
-      // Waiting slots [plo, phi) are built in this tile's division phase.
-      uint32_t phi = 0;
       if constexpr (MODE == MODE_KEYS) {
         // Written out once less than the margin is free; stage_n is stable
         // here (after the previous barrier), so the decision is uniform.
         const uint32_t sn = __builtin_amdgcn_readfirstlane(sh.stage_n);
-        phi = sn;
-        if (sn > static_cast<uint32_t>(Sh::kStage - Sh::kMargin)) {
-          build_pending<T, BLOCK>(sh, P, plo, min(sn, static_cast<uint32_t>(Sh::kStage)), px0, pqa, pgrp);
-          flush_stage<T, BLOCK>(sh, P);
-          plo = phi = 0;
-        }
+        if (sn > static_cast<uint32_t>(Sh::kStage - Sh::kMargin)) flush_stage<T, BLOCK>(sh, P);
       }
       const uint32_t cnt = min(static_cast<uint32_t>(T), len - base);
       const uint64_t x0 = start + base;
@@ -451,9 +463,6 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
           lds_div(&sh.tile[pos - base], p, inv32(p));
         }
       }
-      // The previous tile's kept integers become entries while the divisions
-      // wait on LDS (they touch only stage slots).
-      if constexpr (MODE == MODE_KEYS) build_pending<T, BLOCK>(sh, P, plo, phi, px0, pqa, pgrp);
       __syncthreads();
 
       if constexpr (MODE == MODE_RAD) {
@@ -517,32 +526,33 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
         }
         // 2. Wave-local compaction: ballots rank the wave's kept integers,
         // lane 0 reserves their stage slots with one LDS atomic, and each
-        // lane parks its kept integers' radicals in their slots.  Slots past
-        // the stage (a tile that keeps more than the margin left free) are
-        // built at once and go straight to the workgroup's regions.
+        // kept integer writes its tile index into its slot (two bytes, the
+        // only work done per integer with lanes masked off).  The wave then
+        // builds the entries of its slots, one slot per lane, from rad(x)
+        // and rad(x + 1) still in the tile.  Slots past the stage (a tile
+        // that keeps more than the margin left free) are built at once and
+        // go straight to the workgroup's regions.
         if (total) {  // uniform over the wave
           const uint64_t below = (1ull << lane_id()) - 1ull;
           uint32_t sbase = 0;
           if (lane_id() == 0) sbase = atomicAdd(&sh.stage_n, total);
           sbase = __builtin_amdgcn_readfirstlane(sbase);
+          const uint32_t send = min(sbase + total, static_cast<uint32_t>(Sh::kStage));
+          uint32_t sl = sbase;
           if (sbase + total <= static_cast<uint32_t>(Sh::kStage)) {  // the common case: all in the stage
 #pragma unroll
             for (int it = 0; it < ITER; ++it) {
-              if ((mask[it] >> lane_id()) & 1ull) {
-                const uint32_t slot = sbase + __popcll(mask[it] & below);
-                sh.stage[slot] = pack_pending(ra[it], rb[it]);
-                sh.sb[slot] = static_cast<uint16_t>(it * BLOCK + tid);
-              }
-              sbase += __popcll(mask[it]);
+              if ((mask[it] >> lane_id()) & 1ull)
+                sh.sb[sl + __popcll(mask[it] & below)] = static_cast<uint16_t>(it * BLOCK + tid);
+              sl += __popcll(mask[it]);
             }
           } else {
 #pragma unroll
             for (int it = 0; it < ITER; ++it) {
               if ((mask[it] >> lane_id()) & 1ull) {
                 const uint32_t i = it * BLOCK + tid;
-                const uint32_t slot = sbase + __popcll(mask[it] & below);
+                const uint32_t slot = sl + __popcll(mask[it] & below);
                 if (slot < static_cast<uint32_t>(Sh::kStage)) {
-                  sh.stage[slot] = pack_pending(ra[it], rb[it]);
                   sh.sb[slot] = static_cast<uint16_t>(i);
                 } else {
                   uint32_t bk;
@@ -554,14 +564,17 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
                     atomicOr(&P.flags[kFlagL1Overflow], 1u);
                 }
               }
-              sbase += __popcll(mask[it]);
+              sl += __popcll(mask[it]);
             }
           }
+          wave_sync();
+          for (uint32_t sidx = sbase + lane_id(); sidx < send; sidx += 64) {
+            const uint32_t i = sh.sb[sidx];
+            uint32_t bk;
+            sh.stage[sidx] = kept_entry(P, sh.tile[i], sh.tile[i + 1], x0 + i, qa, grp, &bk);
+            sh.sb[sidx] = static_cast<uint16_t>(bk);
+          }
         }
-        plo = phi;  // this tile's slots start where the stage stood at its start
-        px0 = x0;
-        pqa = qa;
-        pgrp = grp;
       }
       __syncthreads();
     }
@@ -569,7 +582,6 @@ __global__ __launch_bounds__(BLOCK) void k_sieve(SieveParams P) {
   if constexpr (MODE == MODE_KEYS) {
     __syncthreads();
     const uint32_t sn = __builtin_amdgcn_readfirstlane(sh.stage_n);
-    build_pending<T, BLOCK>(sh, P, plo, min(sn, static_cast<uint32_t>(Sh::kStage)), px0, pqa, pgrp);
     if (sn > 0) flush_stage<T, BLOCK>(sh, P);
     for (uint32_t b = tid; b <= P.b1mask; b += BLOCK) P.cnt1[static_cast<uint64_t>(b) * gridDim.x + blockIdx.x] = sh.lcur[b];
   }
@@ -667,7 +679,7 @@ __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
     };
     __syncthreads();
     if (n_cur)  // uniform over the workgroup
-      scatter_runs<BLOCK, kB2Max, false>(
+      scatter_runs<BLOCK, kB2Max, kPartChunk, false>(
           n_cur, B2, ent, bucket_of, perm, cnt, gofs, wsum, gcur, cap2, &P.flags[kFlagL2Overflow],
           [=](uint32_t b, uint32_t kk, const Entry& x) { out[static_cast<uint64_t>(b) * cap2 + kk] = x; }, prefetch);
     else
@@ -732,11 +744,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
     uint32_t slots = 1024;
     while (slots < 2 * m && slots < static_cast<uint32_t>(kJoinSlots)) slots <<= 1;
     const uint32_t smask = slots - 1;
+    // Every thread loads all its entries at once: lanes past the chunk load
+    // entry 0 instead (m >= 2), so that no load waits behind a masked one.
     Entry e[EPT];
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       const uint32_t i = tid + k * BLOCK;
-      if (i < m) e[k] = src[i0 + i];
+      e[k] = src[i0 + (i < m ? i : 0u)];
     }
     // Cleared four slots per store (slots is a multiple of 1024).
     for (uint32_t s = 4 * tid; s < slots; s += 4 * BLOCK)
