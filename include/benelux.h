@@ -165,9 +165,12 @@ double bx_now(void);
 /* Autotuner.  Times the batched search of the queries [a[i], b[i]) (q >= 1;
  * one query [1, N+1) stands for a plain search) under every combination of
  * sieve tile {2048, 8192}, segment length {2^15 .. 2^19} and second-level group
- * {2, 4, 8}, `reps` timed runs each after one warm-up, keeps the fastest,
+ * {2, 4, 8}, then, with the fastest of those, every small-query cutoff
+ * {0, 1024, 2048, 4096, 8192} and workgroup size {256, 512, 1024} of that
+ * class; `reps` timed runs per setting after one warm-up.  Keeps the fastest,
  * applies it to ctx and, when path is not NULL, writes it as a one-line JSON
- * object (arch, tile, seg_len, group, ms).  Results of every run are checked
+ * object (arch, tile, seg_len, group, small_max, small_block, ms).  Results of
+ * every run are checked
  * to be identical.  Errors as bx_search_batch, plus BX_EDEVICE when a file
  * cannot be written and BX_EINTERNAL when two settings disagree. */
 int bx_autotune(bx_ctx* ctx, const uint64_t* a, const uint64_t* b, size_t q, int reps, const char* path);
@@ -184,8 +187,8 @@ typedef struct {
   uint64_t entries;           /* entries written by all passes                    */
   uint64_t candidates;        /* candidate pairs emitted by the join              */
   uint64_t pairs;             /* verified pairs reported (kinds filter applied)   */
-  uint32_t launches[5];       /* launches per kernel: sieve, partition, join, verify, radicals */
-  double kernel_ms[5];        /* summed device time per kernel, same order        */
+  uint32_t launches[6];       /* launches per kernel: sieve, partition, join, verify, radicals, small */
+  double kernel_ms[6];        /* summed device time per kernel, same order        */
   double total_ms;            /* host wall time of the call                       */
   uint32_t b1_bits, b2_bits;  /* partition fan-outs used                          */
   uint32_t seg_len, tile;     /* segment length and LDS tile used by the sieve    */
@@ -219,7 +222,14 @@ int bx_get_stats(bx_ctx* ctx, bx_stats* out);
  *                  join (default 1; the pair lists are the same either way:
  *                  a pair's larger member n has n and n+1 non-squarefree, and
  *                  a squarefree smaller member m has n or n+1 = m*t with
- *                  t >= max(2, rad(m+1) - 1), likewise for m+1)  */
+ *                  t >= max(2, rad(m+1) - 1), likewise for m+1)
+ *   "small_max"    queries of 2 .. small_max integers (at most 8192; 0 = none)
+ *                  are each sieved, member-tested and hash-joined by one
+ *                  workgroup in LDS, with no entry written to device memory
+ *                  and no partition or join launch (default 8192; the pairs
+ *                  are the same either way)
+ *   "small_block"  threads per workgroup of that class: 256, 512 or 1024
+ *                  (0 = 1024)  */
 int bx_set_option(bx_ctx* ctx, const char* name, int64_t value);
 
 void bx_free(void* p);

@@ -44,7 +44,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("passes", ctypes.c_uint32), ("retries", ctypes.c_uint32),
                 ("integers", ctypes.c_uint64), ("entries", ctypes.c_uint64),
                 ("candidates", ctypes.c_uint64), ("pairs", ctypes.c_uint64),
-                ("launches", ctypes.c_uint32 * 5), ("kernel_ms", ctypes.c_double * 5),
+                ("launches", ctypes.c_uint32 * 6), ("kernel_ms", ctypes.c_double * 6),
                 ("total_ms", ctypes.c_double), ("b1_bits", ctypes.c_uint32), ("b2_bits", ctypes.c_uint32),
                 ("seg_len", ctypes.c_uint32), ("tile", ctypes.c_uint32), ("graph_ms", ctypes.c_double),
                 ("joined", ctypes.c_uint64), ("false_candidates", ctypes.c_uint64)]

@@ -63,7 +63,7 @@ class Benelux:
     def stats(self):
         st = Stats()
         check(self._lib.bx_get_stats(self._h, ctypes.byref(st)))
-        names = ["sieve", "partition", "join", "verify", "radicals"]
+        names = ["sieve", "partition", "join", "verify", "radicals", "small"]
         return {
             "passes": st.passes, "retries": st.retries, "integers": st.integers, "entries": st.entries,
             "candidates": st.candidates, "pairs": st.pairs,

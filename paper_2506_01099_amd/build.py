@@ -6,7 +6,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbenelux.so")
 SOURCES = [os.path.join(HERE, "csrc", "benelux.hip")]
-DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("bx_device.h", "bx_kernels.h")] + [
+DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("bx_device.h", "bx_kernels.h", "bx_alg3.h", "bx_small.h")] + [
     os.path.join(ROOT, "include", "benelux.h")]
 
 HIPCC_FLAGS = [

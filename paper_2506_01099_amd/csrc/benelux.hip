@@ -23,6 +23,7 @@
 
 #include "bx_alg3.h"
 #include "bx_kernels.h"
+#include "bx_small.h"
 
 using namespace bx;
 
@@ -55,7 +56,11 @@ constexpr uint32_t kDefaultSegLen = 1u << 18;
 constexpr uint64_t kMaxQueryLen = 1ull << 28;
 constexpr uint32_t kMaxQueries = kGrpMask + 1;
 
-enum { K_SIEVE = 0, K_PART = 1, K_JOIN = 2, K_VERIFY = 3, K_RAD = 4 };
+enum { K_SIEVE = 0, K_PART = 1, K_JOIN = 2, K_VERIFY = 3, K_RAD = 4, K_SMALL = 5 };
+
+// Queries of at most this many integers are served whole by one workgroup
+// (k_small) when the small-query class is on; the class keeps no HBM entries.
+constexpr uint32_t kSmallMaxLen = 8192;
 
 double now_s() {
   using namespace std::chrono;
@@ -108,7 +113,7 @@ struct bx_ctx {
   uint32_t* d_primes = nullptr;
   PrimePow* d_pp = nullptr;
   DenseTab* d_dense[2] = {nullptr, nullptr};
-  DevBuf l1, l2, cnt1, cnt2, cand, out, flags, spill, queries, segpref, rad, acc, a3tab;
+  DevBuf l1, l2, cnt1, cnt2, cand, out, flags, spill, queries, segpref, rad, acc, a3tab, smallq;
   int force_passes = 0, timing = 1, force_b1 = -1, force_b2 = -1, force_group = 0;
   int prune = 1;            // drop x that cannot be a pair member before the join
   int join_sort = 0;        // 1: the sort join per partition (ablation of the hash join)
@@ -119,10 +124,13 @@ struct bx_ctx {
   // partition bits) and a few low ones to make different sets collide.
   uint64_t fp_mask = (1ull << kFpBits) - 1;
   int tile = kTileDefault;
+  uint32_t small_max = kSmallMaxLen;  // longest query of the small class (0: class off)
+  int small_block = 1024;             // threads of a small-class workgroup
   int graph_batch = 1;      // batched calls run as one captured HIP graph
   bool capturing = false;   // no event records while a stream capture is open
   hipGraphExec_t graph_exec = nullptr;
   std::string graph_key;
+  uint32_t graph_launches[6] = {0, 0, 0, 0, 0, 0};  // kernel launches the graph holds, per kernel
   uint32_t seg_len = kDefaultSegLen;
   bx_stats stats{};
   std::mutex mu;
@@ -378,6 +386,7 @@ int make_plan(bx_ctx* c, uint64_t n_keys, uint64_t n_expect, uint64_t share, uin
 struct Segs {
   std::vector<Query> q;
   std::vector<uint64_t> prefix;
+  std::vector<uint32_t> small;  // queries served by the small-query class (no segments)
   uint64_t n_segs = 0;
   uint64_t n_ints = 0;  // integers sieved
   uint64_t n_keys = 0;    // bound on the entries they produce (all of them without the member test)
@@ -474,7 +483,7 @@ uint64_t max_share(const bx_ctx* c, const Segs& s, uint32_t W) {
   for (size_t i = 0; i < s.q.size(); ++i) {
     const Query& q = s.q[i];
     const uint64_t len = q.b > q.a ? q.b - q.a : 0;
-    if (len == 0) continue;
+    if (len == 0 || s.prefix[i + 1] == s.prefix[i]) continue;  // empty or small-class
     const uint64_t nseg = (len + L - 1) / L, nfull = nseg - 1;
     // Full segments, split where the zone changes.
     uint64_t k = 0;
@@ -501,9 +510,10 @@ uint64_t max_share(const bx_ctx* c, const Segs& s, uint32_t W) {
   // times an even spread over the query's segments.
   double spread = 0.0;
   for (size_t i = 0; i < s.q.size(); ++i) {
+    const uint64_t nseg = s.prefix[i + 1] - s.prefix[i];
+    if (nseg == 0) continue;
     const double sc = scattered(c, s.q[i]);
     if (sc == 0.0) continue;
-    const uint64_t nseg = s.prefix[i + 1] - s.prefix[i];
     const double per = 4.0 * sc * static_cast<double>((nseg + W - 1) / W) / static_cast<double>(std::max<uint64_t>(1, nseg));
     spread += std::min(sc, per) + 64.0;
   }
@@ -515,14 +525,26 @@ uint64_t max_share(const bx_ctx* c, const Segs& s, uint32_t W) {
   return static_cast<uint64_t>(std::ceil(best + spread));
 }
 
+// Whether query q is served by the small-query class.
+bool is_small(const bx_ctx* c, const Query& q) {
+  const uint64_t L = q.b > q.a ? q.b - q.a : 0;
+  return L >= 2 && L <= c->small_max;
+}
+
 void make_segs(const bx_ctx* c, Segs* s) {
   s->prefix.assign(s->q.size() + 1, 0);
+  s->small.clear();
   s->n_ints = 0;
   uint64_t acc = 0;
   double keys = 0.0, expect = 0.0;
   for (size_t i = 0; i < s->q.size(); ++i) {
     s->prefix[i] = acc;
     const uint64_t L = s->q[i].b > s->q[i].a ? s->q[i].b - s->q[i].a : 0;
+    if (is_small(c, s->q[i])) {
+      s->small.push_back(static_cast<uint32_t>(i));
+      s->n_ints += L;
+      continue;
+    }
     acc += (L + c->seg_len - 1) / c->seg_len;
     keys += kept_bound(c, s->q[i], s->q[i].a, s->q[i].b);
     expect += kept_expected(c, s->q[i]);
@@ -540,6 +562,10 @@ int upload_segs(bx_ctx* c, const Segs& s, hipStream_t st) {
   if ((rc = ensure(c, c->segpref, s.prefix.size() * sizeof(uint64_t))) != BX_OK) return rc;
   BX_HIP(hipMemcpyAsync(c->queries.p, s.q.data(), s.q.size() * sizeof(Query), hipMemcpyHostToDevice, st));
   BX_HIP(hipMemcpyAsync(c->segpref.p, s.prefix.data(), s.prefix.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  if (!s.small.empty()) {
+    if ((rc = ensure(c, c->smallq, s.small.size() * sizeof(uint32_t))) != BX_OK) return rc;
+    BX_HIP(hipMemcpyAsync(c->smallq.p, s.small.data(), s.small.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+  }
   // The host vectors die with the caller: wait for the copies.
   BX_HIP(hipStreamSynchronize(st));
   return BX_OK;
@@ -597,7 +623,7 @@ struct Job {
 
 // Bytes of every workspace buffer a job needs.
 struct JobBufs {
-  size_t l1, l2, cnt1, cnt2, cand, out, flags, acc, spill, queries, segpref;
+  size_t l1, l2, cnt1, cnt2, cand, out, flags, acc, spill, queries, segpref, smallq;
 };
 
 // The plan and launch shapes of one search over `s` and the workspace it
@@ -636,6 +662,8 @@ int plan_job(bx_ctx* c, Segs& s, int batch, uint32_t kinds, Job* j, JobBufs* nb)
   nb->spill = static_cast<size_t>(j->sieve_grid) * spill_cap_of(c) * 8;
   nb->queries = s.q.size() * sizeof(Query);
   nb->segpref = s.prefix.size() * sizeof(uint64_t);
+  nb->smallq = s.small.size() * sizeof(uint32_t);
+  if (s.n_segs == 0) j->plan.passes = 0;  // small-class queries only
   return BX_OK;
 }
 
@@ -647,7 +675,8 @@ uint64_t bytes_after(const bx_ctx* c, const JobBufs& nb, bool released) {
                                                 {&c->cand, nb.cand},   {&c->out, nb.out},
                                                 {&c->flags, nb.flags}, {&c->acc, nb.acc},
                                                 {&c->spill, nb.spill}, {&c->queries, nb.queries},
-                                                {&c->segpref, nb.segpref}, {&c->rad, 0}};
+                                                {&c->segpref, nb.segpref}, {&c->smallq, nb.smallq},
+                                                {&c->rad, 0}};
   uint64_t t = 0;
   for (const auto& e : v) t += std::max<uint64_t>(released ? 0 : e.first->bytes, std::max<size_t>(e.second, 256));
   return t;
@@ -757,6 +786,57 @@ int enqueue_pass(bx_ctx* c, const Job& j, uint64_t ph_lo, uint64_t ph_hi, hipStr
   return BX_OK;
 }
 
+// The small-query class: one workgroup per query of at most small_max
+// integers sieves, tests and joins it in LDS; its candidates join those of the
+// passes in the candidate buffer.
+int enqueue_small(bx_ctx* c, const Job& j, hipStream_t st) {
+  const Segs& s = *j.s;
+  if (s.small.empty()) return BX_OK;
+  SmallParams P;
+  P.queries = static_cast<const Query*>(c->queries.p);
+  P.list = static_cast<const uint32_t*>(c->smallq.p);
+  P.batch = j.batch;
+  P.prune = c->prune;
+  P.pp = c->d_pp;
+  P.n_pp = static_cast<uint32_t>(c->pp.size());
+  const bool big = c->small_max > static_cast<uint32_t>(kTileSmall);
+  P.n_dense = c->n_dense[big ? 1 : 0];
+  P.dense = c->d_dense[big ? 1 : 0];
+  P.fp_mask = c->fp_mask;
+  P.cand = static_cast<Cand*>(c->cand.p);
+  P.cand_cap = kCandCap;
+  P.flags = static_cast<uint32_t*>(c->flags.p);
+  P.acc = static_cast<unsigned long long*>(c->acc.p);
+  for (uint32_t qi : s.small) {
+    const Query& q = s.q[qi];
+    if (q.b - q.a < 2 || q.b - q.a > (big ? kTileLarge : kTileSmall))
+      return fail(BX_EINTERNAL, "small-class query outside the class bounds");
+  }
+  const dim3 grid(static_cast<uint32_t>(s.small.size()));
+  {
+    LaunchTimer t(c, K_SMALL, st);
+#define BX_SMALL_LAUNCH(T, B) hipLaunchKernelGGL((k_small<T, B>), grid, dim3(B), 0, st, P)
+    if (big) {
+      if (c->small_block == 256)
+        BX_SMALL_LAUNCH(kTileLarge, 256);
+      else if (c->small_block == 512)
+        BX_SMALL_LAUNCH(kTileLarge, 512);
+      else
+        BX_SMALL_LAUNCH(kTileLarge, 1024);
+    } else {
+      if (c->small_block == 256)
+        BX_SMALL_LAUNCH(kTileSmall, 256);
+      else if (c->small_block == 512)
+        BX_SMALL_LAUNCH(kTileSmall, 512);
+      else
+        BX_SMALL_LAUNCH(kTileSmall, 1024);
+    }
+#undef BX_SMALL_LAUNCH
+  }
+  BX_HIP(hipGetLastError());
+  return BX_OK;
+}
+
 int enqueue_verify(bx_ctx* c, const Job& j, uint32_t grid, hipStream_t st) {
   VerifyParams V;
   V.cand = static_cast<const Cand*>(c->cand.p);
@@ -820,12 +900,19 @@ int collect_pairs(bx_ctx* c, const uint32_t* fl, hipStream_t st, std::vector<Out
 int run_passes_checked(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* result) {
   int rc;
   if ((rc = enqueue_init(c, j, st)) != BX_OK) return rc;
+  if ((rc = enqueue_small(c, j, st)) != BX_OK) return rc;
   std::deque<std::pair<uint64_t, uint64_t>> pending;
   for (uint64_t v = 0; v < j.plan.passes; ++v)
     pending.emplace_back((v << 32) / j.plan.passes, ((v + 1) << 32) / j.plan.passes);
   uint32_t cand_before = 0;
   unsigned long long acc_before[kAccCount] = {0, 0};
   uint32_t fl[kFlagCount];
+  if (!j.s->small.empty()) {  // a split pass rolls back to what the small class left
+    if ((rc = read_flags(c, fl, st)) != BX_OK) return rc;
+    cand_before = fl[kFlagCand];
+    BX_HIP(hipMemcpyAsync(acc_before, c->acc.p, sizeof(acc_before), hipMemcpyDeviceToHost, st));
+    BX_HIP(hipStreamSynchronize(st));
+  }
   while (!pending.empty()) {
     const uint64_t ph_lo = pending.front().first, ph_hi = pending.front().second;
     pending.pop_front();
@@ -870,21 +957,24 @@ int run_passes_graph(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* re
   // Every launch shape, every option baked into a kernel argument or choice,
   // and every buffer address the graph's kernels use.
   std::snprintf(key, sizeof(key),
-                "%u %llu %u %u %u %u %llu %u %d %u %u %d %u %d %d %llx %p %p %p %p %p %p %p %p %p %p %p %p %p",
+                "%u %llu %u %u %u %u %llu %u %d %u %u %d %u %d %d %llx %u %d %zu %p %p %p %p %p %p %p %p %p %p %p %p %p %p",
                 j.plan.passes, static_cast<unsigned long long>(j.plan.cap1), j.plan.cap2, j.plan.b1bits, j.plan.b2bits,
                 j.G, static_cast<unsigned long long>(j.s->n_segs), static_cast<uint32_t>(j.s->q.size()), j.batch,
                 j.kinds, c->third_off, c->tile, c->seg_len, c->prune, c->join_sort,
-                static_cast<unsigned long long>(c->fp_mask), c->l1.p, c->l2.p, c->spill.p, c->cnt1.p, c->cnt2.p,
-                c->cand.p, c->out.p, c->flags.p, c->acc.p, c->queries.p, c->segpref.p, static_cast<void*>(c->d_pp),
-                static_cast<void*>(c->d_primes));
+                static_cast<unsigned long long>(c->fp_mask), c->small_max, c->small_block, j.s->small.size(), c->l1.p,
+                c->l2.p, c->spill.p, c->cnt1.p, c->cnt2.p, c->cand.p, c->out.p, c->flags.p, c->acc.p, c->queries.p,
+                c->segpref.p, c->smallq.p, static_cast<void*>(c->d_pp), static_cast<void*>(c->d_primes));
   if (!c->graph_exec || c->graph_key != key) {
     if (c->graph_exec) {
       BX_HIP(hipGraphExecDestroy(c->graph_exec));
       c->graph_exec = nullptr;
     }
+    uint32_t before[6];
+    std::memcpy(before, c->stats.launches, sizeof(before));
     BX_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     c->capturing = true;
     rc = enqueue_init(c, j, st);
+    if (rc == BX_OK) rc = enqueue_small(c, j, st);
     for (uint64_t v = 0; rc == BX_OK && v < j.plan.passes; ++v)
       rc = enqueue_pass(c, j, (v << 32) / j.plan.passes, ((v + 1) << 32) / j.plan.passes, st);
     if (rc == BX_OK) rc = enqueue_verify(c, j, kVerifyGrid, st);
@@ -900,6 +990,9 @@ int run_passes_graph(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* re
     (void)hipGraphDestroy(g);
     BX_HIP(e);
     c->graph_key = key;
+    for (int k = 0; k < 6; ++k) c->graph_launches[k] = c->stats.launches[k] - before[k];
+  } else {
+    for (int k = 0; k < 6; ++k) c->stats.launches[k] += c->graph_launches[k];
   }
   hipEvent_t a = get_event(c), b = get_event(c);
   if (a) BX_HIP(hipEventRecord(a, st));
@@ -930,7 +1023,7 @@ int run_search(bx_ctx* c, Segs& s, int batch, uint32_t kinds, std::vector<OutPai
   rc = mark_done(c, st);  // host-synchronous from here on: the call drains st
   if (rc != BX_OK) return rc;
   make_segs(c, &s);
-  if (s.n_segs == 0) return BX_OK;
+  if (s.n_segs == 0 && s.small.empty()) return BX_OK;
   Job j;
   if ((rc = prepare_job(c, s, batch, kinds, st, &j)) != BX_OK) return rc;
   c->stats.integers = s.n_ints;
@@ -1144,7 +1237,7 @@ namespace {
 uint64_t workspace_bytes(const bx_ctx* c) {
   uint64_t t = 0;
   for (const DevBuf* b : {&c->l1, &c->l2, &c->cnt1, &c->cnt2, &c->cand, &c->out, &c->flags, &c->spill, &c->queries,
-                          &c->segpref, &c->rad, &c->acc})
+                          &c->segpref, &c->rad, &c->acc, &c->smallq})
     t += b->bytes;
   return t;
 }
@@ -1154,7 +1247,7 @@ void release_workspace(bx_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   for (DevBuf* b : {&c->l1, &c->l2, &c->cnt1, &c->cnt2, &c->cand, &c->out, &c->flags, &c->spill, &c->queries,
-                    &c->segpref, &c->rad, &c->acc})
+                    &c->segpref, &c->rad, &c->acc, &c->smallq})
     free_buf(*b);
   if (c->graph_exec) {
     (void)hipGraphExecDestroy(c->graph_exec);
@@ -1337,7 +1430,7 @@ void bx_destroy(bx_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (DevBuf* b : {&c->l1, &c->l2, &c->cnt1, &c->cnt2, &c->cand, &c->out, &c->flags, &c->spill, &c->queries,
-                    &c->segpref, &c->rad, &c->acc, &c->a3tab})
+                    &c->segpref, &c->rad, &c->acc, &c->a3tab, &c->smallq})
     free_buf(*b);
   if (c->d_primes) (void)hipFree(c->d_primes);
   if (c->d_pp) (void)hipFree(c->d_pp);
@@ -1400,6 +1493,12 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
   } else if (n == "group") {
     if (v != 0 && v != 1 && v != 2 && v != 4 && v != 8) return fail(BX_EINVAL, "group must be 0, 1, 2, 4 or 8");
     c->force_group = static_cast<int>(v);
+  } else if (n == "small_max") {
+    if (v < 0 || v > static_cast<int64_t>(kSmallMaxLen)) return fail(BX_EINVAL, "small_max must be in [0, 8192]");
+    c->small_max = static_cast<uint32_t>(v);
+  } else if (n == "small_block") {
+    if (v != 0 && v != 256 && v != 512 && v != 1024) return fail(BX_EINVAL, "small_block must be 0, 256, 512 or 1024");
+    c->small_block = v == 0 ? 1024 : static_cast<int>(v);
   } else if (n == "b1_bits") {
     if (v > 10) return fail(BX_EINVAL, "b1_bits <= 10");
     c->force_b1 = v == 0 ? -1 : static_cast<int>(v);
@@ -1631,6 +1730,8 @@ int bx_serve_start(bx_ctx* c, uint64_t budget_bytes, int max_inflight) {
     lane->fp_mask = c->fp_mask;
     lane->third_off = c->third_off;
     lane->force_group = c->force_group;
+    lane->small_max = c->small_max;
+    lane->small_block = c->small_block;
     lane->timing = 0;
     lane->graph_batch = 0;  // batch shapes change from batch to batch: no graph reuse
     S->lanes.push_back(lane);
@@ -1742,80 +1843,103 @@ int bx_serve_get_info(bx_ctx* c, bx_serve_info* out) {
   return BX_OK;
 }
 
+// One timed setting of the autotuner: the best of `reps` batched runs after
+// one warm-up, each checked against the first result seen (*ref).
+int tune_one(bx_ctx* c, const uint64_t* a, const uint64_t* b, size_t q, int reps, std::vector<OutPair>* ref,
+             bool* have_ref, double* t_best) {
+  int rc = BX_OK;
+  *t_best = 1e300;
+  for (int r = 0; r <= reps && rc == BX_OK; ++r) {
+    std::lock_guard<std::mutex> lk(c->mu);
+    reset_stats(c);
+    Segs s;
+    for (size_t i = 0; i < q; ++i) {
+      const uint64_t ai = a[i] == 0 ? 1 : a[i];
+      uint64_t bi = b[i] < ai ? ai : b[i];
+      if (bi - ai > kMaxQueryLen) return fail(BX_EINVAL, "query longer than 2^28");
+      if (bi > ai + 1 && (rc = check_query(c, ai, bi, BX_BOTH)) != BX_OK) return rc;
+      if (bi <= ai + 1) bi = ai;
+      s.q.push_back(Query{ai, bi});
+    }
+    BX_HIP(hipSetDevice(c->device));
+    std::vector<OutPair> res;
+    const double t0 = now_s();
+    rc = run_search(c, s, 1, BX_BOTH, &res, c->graph_batch != 0);
+    (void)hipStreamSynchronize(c->stream);
+    const double ms = (now_s() - t0) * 1e3;
+    collect_timings(c);
+    if (rc != BX_OK) return rc;
+    if (!*have_ref) {
+      *ref = res;
+      *have_ref = true;
+    } else if (res.size() != ref->size() ||
+               !std::equal(res.begin(), res.end(), ref->begin(), [](const OutPair& x, const OutPair& y) {
+                 return x.m == y.m && x.n == y.n && x.kind == y.kind && x.query == y.query;
+               })) {
+      return fail(BX_EINTERNAL, "autotune: results differ between settings");
+    }
+    if (r > 0) *t_best = std::min(*t_best, ms);
+  }
+  return rc;
+}
+
 int bx_autotune(bx_ctx* c, const uint64_t* a, const uint64_t* b, size_t q, int reps, const char* path) {
   if (!c || !a || !b || q == 0 || reps < 1) return fail(BX_EINVAL, "bad autotune arguments");
   if (q > kMaxQueries) return fail(BX_EINVAL, "at most 32768 queries per batch");
-  const int saved_tile = c->tile, saved_group = c->force_group;
-  const uint32_t saved_seg = c->seg_len;
+  const int saved_tile = c->tile, saved_group = c->force_group, saved_sblock = c->small_block;
+  const uint32_t saved_seg = c->seg_len, saved_smax = c->small_max;
   struct Best {
     int tile = kTileSmall, group = 8;
     uint32_t seg = kDefaultSegLen;
+    uint32_t small_max = kSmallMaxLen;
+    int small_block = 1024;
     double ms = 1e300;
   } best;
   std::vector<OutPair> ref;
   bool have_ref = false;
   int rc = BX_OK;
+  auto set = [&](int tile, uint32_t seg, int group, uint32_t smax, int sblock) {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->tile = tile;
+    c->seg_len = seg;
+    c->force_group = group;
+    c->small_max = smax;
+    c->small_block = sblock;
+  };
+  // The passes' shape first, with the small-query class at its default ...
   for (int tile : {kTileSmall, kTileLarge}) {
     for (uint32_t seg : {1u << 15, 1u << 16, 1u << 17, 1u << 18, 1u << 19}) {
       for (int group : {2, 4, 8}) {
-        double t_best = 1e300;
-        for (int r = 0; r <= reps && rc == BX_OK; ++r) {
-          std::lock_guard<std::mutex> lk(c->mu);
-          c->tile = tile;
-          c->seg_len = seg;
-          c->force_group = group;
-          reset_stats(c);
-          Segs s;
-          for (size_t i = 0; i < q; ++i) {
-            const uint64_t ai = a[i] == 0 ? 1 : a[i];
-            uint64_t bi = b[i] < ai ? ai : b[i];
-            if (bi - ai > kMaxQueryLen) rc = fail(BX_EINVAL, "query longer than 2^28");
-            if (bi > ai + 1 && rc == BX_OK) rc = check_query(c, ai, bi, BX_BOTH);
-            if (bi <= ai + 1) bi = ai;
-            s.q.push_back(Query{ai, bi});
-          }
-          if (rc != BX_OK) break;
-          BX_HIP(hipSetDevice(c->device));
-          std::vector<OutPair> res;
-          const double t0 = now_s();
-          rc = run_search(c, s, 1, BX_BOTH, &res, c->graph_batch != 0);
-          (void)hipStreamSynchronize(c->stream);
-          const double ms = (now_s() - t0) * 1e3;
-          collect_timings(c);
-          if (rc != BX_OK) break;
-          if (!have_ref) {
-            ref = res;
-            have_ref = true;
-          } else if (res.size() != ref.size() ||
-                     !std::equal(res.begin(), res.end(), ref.begin(), [](const OutPair& x, const OutPair& y) {
-                       return x.m == y.m && x.n == y.n && x.kind == y.kind && x.query == y.query;
-                     })) {
-            rc = fail(BX_EINTERNAL, "autotune: results differ between settings");
-          }
-          if (r > 0) t_best = std::min(t_best, ms);
-        }
         if (rc != BX_OK) break;
-        if (t_best < best.ms) best = Best{tile, group, seg, t_best};
+        set(tile, seg, group, saved_smax, saved_sblock);
+        double t = 0.0;
+        rc = tune_one(c, a, b, q, reps, &ref, &have_ref, &t);
+        if (rc == BX_OK && t < best.ms) best = Best{tile, group, seg, saved_smax, saved_sblock, t};
       }
-      if (rc != BX_OK) break;
     }
-    if (rc != BX_OK) break;
   }
-  std::lock_guard<std::mutex> lk(c->mu);
+  // ... then the class's cutoff and workgroup size with that shape.
+  for (uint32_t smax : {0u, 1024u, 2048u, 4096u, 8192u}) {
+    for (int sblock : {256, 512, 1024}) {
+      if (rc != BX_OK || (smax == 0 && sblock != 1024)) continue;
+      set(best.tile, best.seg, best.group, smax, sblock);
+      double t = 0.0;
+      rc = tune_one(c, a, b, q, reps, &ref, &have_ref, &t);
+      if (rc == BX_OK && t < best.ms) best = Best{best.tile, best.group, best.seg, smax, sblock, t};
+    }
+  }
   if (rc != BX_OK) {
-    c->tile = saved_tile;
-    c->seg_len = saved_seg;
-    c->force_group = saved_group;
+    set(saved_tile, saved_seg, saved_group, saved_smax, saved_sblock);
     return rc;
   }
-  c->tile = best.tile;
-  c->seg_len = best.seg;
-  c->force_group = best.group;
+  set(best.tile, best.seg, best.group, best.small_max, best.small_block);
   if (path) {
     FILE* f = std::fopen(path, "w");
     if (!f) return fail(BX_EDEVICE, std::string("cannot write ") + path);
-    std::fprintf(f, "{\"arch\": \"%s\", \"tile\": %d, \"seg_len\": %u, \"group\": %d, \"ms\": %.3f}\n", c->arch.c_str(),
-                 best.tile, best.seg, best.group, best.ms);
+    std::fprintf(f,
+                 "{\"arch\": \"%s\", \"tile\": %d, \"seg_len\": %u, \"group\": %d, \"small_max\": %u, "
+                 "\"small_block\": %d, \"ms\": %.3f}\n",
+                 c->arch.c_str(), best.tile, best.seg, best.group, best.small_max, best.small_block, best.ms);
     std::fclose(f);
   }
   return BX_OK;
@@ -1849,7 +1973,12 @@ int bx_load_tuning(bx_ctx* c, const char* path) {
   int rc;
   if ((rc = bx_set_option(c, "tile", tile)) != BX_OK) return rc;
   if ((rc = bx_set_option(c, "seg_len", seg)) != BX_OK) return rc;
-  return bx_set_option(c, "group", group);
+  if ((rc = bx_set_option(c, "group", group)) != BX_OK) return rc;
+  // The small-query class fields are optional (files written before the class existed).
+  long long smax = 0, sblock = 0;
+  if (field("small_max", &smax) && (rc = bx_set_option(c, "small_max", smax)) != BX_OK) return rc;
+  if (field("small_block", &sblock) && (rc = bx_set_option(c, "small_block", sblock)) != BX_OK) return rc;
+  return BX_OK;
 }
 
 double bx_now(void) { return now_s(); }

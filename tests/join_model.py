@@ -70,7 +70,7 @@ def kept(x, r0, r1, b):
     return (x <= 3) | ~(drop0 | drop1)
 
 
-def group_keys(rad, a, b, grp, b1_bits, passes, fp_bits):
+def group_keys(rad, a, b, grp, b1_bits, passes, fp_bits, prune=True):
     """For the query [a, b) with rad[i] = rad(a + i), i in [0, b - a], the join group of
     every entry that passes the member test: one uint64 per entry holding its pass,
     first-level bucket, query and kept fingerprint bits.  Entries meet exactly when
@@ -79,7 +79,7 @@ def group_keys(rad, a, b, grp, b1_bits, passes, fp_bits):
     x = np.arange(a, b, dtype=np.int64)
     r = rad.astype(np.int64)
     r0, r1 = r[:n], r[1:n + 1]
-    keep = kept(x, r0, r1, b)
+    keep = kept(x, r0, r1, b) if prune else np.ones(n, dtype=bool)
     u0, u1 = r0[keep].astype(np.uint64), r1[keep].astype(np.uint64)
     lo, hi = np.minimum(u0, u1), np.maximum(u0, u1)
     g = np.full(lo.shape, grp, dtype=np.uint64)

@@ -594,6 +594,121 @@ def test_batch_config_queries_sampled(ctx):
         assert got[i] == oracle.search_range(int(a[i]), int(b[i]))
 
 
+# --- small-query class ------------------------------------------------------------------
+
+def _small_queries(n, seed):
+    """Ranges of 2 .. 8192 integers (lengths log-uniform, plus the class edges) at
+    magnitudes from 2^4 to 2^41, and a few just past the class's largest length."""
+    from paper_2506_01099_amd.inputs import SplitMix64
+
+    g = SplitMix64(seed)
+    qs = [(1, 3), (1, 9), (2, 9), (1, 8193), (1, 2049), (35, 4375), (126, 8190), ((1 << 41) - 8192, 1 << 41),
+          ((1 << 42) - 8194, (1 << 42) - 2), (5 << 30, (5 << 30) + 2), (5 << 30, (5 << 30) + 2048),
+          (5 << 30, (5 << 30) + 2049), (7 << 33, (7 << 33) + 8193), (3 << 20, (3 << 20) + 4096)]
+    for _ in range(n):
+        L = int(2.0 ** (1 + 12 * g.unit()))
+        bits = 4 + int(37 * g.unit())
+        a = 1 + (g.next() >> (64 - bits))
+        qs.append((a, a + max(2, L)))
+    a = np.array([q[0] for q in qs], dtype=np.uint64)
+    b = np.array([q[1] for q in qs], dtype=np.uint64)
+    return a, b
+
+
+@pytest.mark.parametrize("small_max,block", [(8192, 1024), (8192, 512), (8192, 256), (2048, 1024), (2048, 256),
+                                             (1024, 512)])
+def test_small_class_matches_oracle(ctx, small_max, block):
+    """Queries sieved, member-tested and joined inside one workgroup (each cutoff and
+    workgroup size) against the oracle, batched and one by one, graph and eager."""
+    a, b = _small_queries(120, seed=small_max + block)
+    want = [oracle.search_range(int(x), int(y)) for x, y in zip(a, b)]
+    ctx.set_option("small_max", small_max)
+    ctx.set_option("small_block", block)
+    try:
+        got = ctx.search_batch(a, b)
+        st = ctx.stats()
+        ctx.set_option("graph", 0)
+        eager = ctx.search_batch(a, b)
+        ctx.set_option("graph", 1)
+        one = [ctx.search_range(int(x), int(y)) for x, y in zip(a[:24], b[:24])]
+        st_one = ctx.stats()
+    finally:
+        ctx.set_option("small_max", 8192)
+        ctx.set_option("small_block", 0)
+        ctx.set_option("graph", 1)
+    n_small = int(np.count_nonzero((b - a) <= small_max))
+    assert st["launches"]["small"] == 1 and n_small > 50
+    assert got == eager == want
+    assert one == want[:24]
+    assert st_one["launches"]["small"] == (1 if int(b[23] - a[23]) <= small_max else 0)
+    assert any(want), "some query holds a pair"
+
+
+def test_small_class_prune_off_and_kinds(ctx):
+    a, b = _small_queries(40, seed=5)
+    ctx.set_option("prune", 0)
+    try:
+        got = ctx.search_batch(a, b, kinds=1)
+        st = ctx.stats()
+    finally:
+        ctx.set_option("prune", 1)
+    assert got == [oracle.search_range(int(x), int(y), 1) for x, y in zip(a, b)]
+    small = (b - a) <= 8192
+    assert st["entries"] >= int((b - a)[small].sum())
+
+
+def test_small_class_candidates_exact(ctx):
+    """Join completeness inside the class, counted exactly: with 12 + 11 fingerprint bits
+    kept and every integer joined (member test off), the kept sets of a query collide
+    (about 4 per query of 8192), and the workgroup's hash table must report every pair of
+    equal (query, fingerprint) -- one table per query, no bucket or pass."""
+    from paper_2506_01099_amd.inputs import SplitMix64
+
+    g = SplitMix64(77)
+    qs = [(1, 8193), (1 << 20, (1 << 20) + 8192), (5 << 30, (5 << 30) + 5000), (1 << 12, 1 << 13)]
+    for _ in range(44):
+        a = 1 + (g.next() >> (64 - 4 - int(36 * g.unit())))
+        qs.append((a, a + 8192))
+    ctx.set_option("fp_bits", 12)
+    ctx.set_option("prune", 0)
+    try:
+        got = ctx.search_batch(np.array([q[0] for q in qs], dtype=np.uint64),
+                               np.array([q[1] for q in qs], dtype=np.uint64))
+        st = ctx.stats()
+    finally:
+        ctx.set_option("fp_bits", 0)
+        ctx.set_option("prune", 1)
+    want, kept = 0, 0
+    for i, (a, b) in enumerate(qs):
+        assert got[i] == oracle.search_range(a, b)
+        keys, n_kept = join_model.group_keys(oracle.radicals(a, b + 1), a, b, i, 0, 1, 12, prune=False)
+        want += join_model.candidates(keys)
+        kept += n_kept
+    assert st["launches"]["small"] == 1 and st["launches"]["sieve"] == 0
+    assert st["entries"] == st["joined"] == kept == sum(b - a for a, b in qs)
+    assert want > 100
+    assert st["candidates"] == want
+    assert st["candidates"] == st["pairs"] + st["false_candidates"]
+
+
+def test_small_class_on_off_same_results(ctx):
+    """The 4096-query batched workload and a low-magnitude mix: identical pair lists with
+    the class off, at 2048 and at 8192."""
+    from paper_2506_01099_amd.inputs import batched_queries
+
+    for a, b in (batched_queries(), batched_queries(n=512, seed=3, log2_min=1, log2_max=16, a_bits=24)):
+        res = []
+        for small_max in (0, 2048, 8192):
+            ctx.set_option("small_max", small_max)
+            try:
+                res.append(ctx.search_batch(a, b))
+                st = ctx.stats()
+            finally:
+                ctx.set_option("small_max", 8192)
+            assert st["launches"]["small"] == (1 if small_max else 0)
+        assert res[0] == res[1] == res[2]
+
+
 # --- served ---------------------------------------------------------------------------
 
 def test_served_alone_equals_in_mix(ctx):
