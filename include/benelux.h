@@ -51,7 +51,8 @@ enum {
   BX_ERANGE = -2,    /* a value needs a radical beyond hi_max or BX_VALUE_LIMIT         */
   BX_ENOMEM = -3,    /* host or device allocation failed, or the HBM budget is too small */
   BX_EDEVICE = -4,   /* a HIP runtime error; the message names it                       */
-  BX_EBUSY = -5,     /* serving: admission refused (budget or slots) with wait = 0      */
+  BX_EBUSY = -5,     /* serving: request beyond the budget, or not admissible at once
+                        with option submit_wait = 0; bx_take of an unfinished request */
   BX_EINTERNAL = -6  /* a device-side consistency check failed (see bx_last_error)     */
 };
 
@@ -116,8 +117,14 @@ int bx_radical_segment_dev_noalloc(bx_ctx* ctx, uint64_t lo, uint64_t hi, uint64
  * *out is malloc'd, *count set.  N + 1 <= hi_max. */
 int bx_benelux_search(bx_ctx* ctx, uint64_t N, uint32_t kinds, bx_pair** out, size_t* count);
 
-/* Range form: pairs with max(a,1) <= m < n < b (radicals over [max(a,1), b]).
- * bx_benelux_search(N) equals bx_search_range(1, N + 1).  b <= hi_max. */
+/* Range form: pairs with max(a,1) <= m < n < b (radicals over [max(a,1), b]),
+ * both members inside the range: Algorithm 3 reports the pairs whose larger
+ * member lies in the chunk it holds, Algorithm 1 sieves an interval
+ * [start, start + length[, and this call does both for one interval.
+ * bx_benelux_search(N) equals bx_search_range(1, N + 1).  b <= hi_max.
+ * Errors: BX_EINVAL (NULL pointer, kinds not in 1..7), BX_ERANGE (b beyond
+ * hi_max), BX_ENOMEM, BX_EDEVICE, BX_EINTERNAL.  a = 0 is read as 1; fewer
+ * than two integers give no pair. */
 int bx_search_range(bx_ctx* ctx, uint64_t a, uint64_t b, uint32_t kinds, bx_pair** out, size_t* count);
 
 /* Batched range queries: for each i < q, the pairs inside [a[i], b[i]) (each
@@ -137,15 +144,22 @@ int bx_search_batch(bx_ctx* ctx, const uint64_t* a, const uint64_t* b, size_t q,
  * bytes of all lanes' workspaces -- this lane's grown to what the batch's plan
  * needs -- stay within budget_bytes (0 = half the owner's budget); a lane that
  * finds no room lets its own idle workspace go.  Batches of different lanes
- * overlap on the device.  bx_submit never blocks; it returns BX_EBUSY when
- * the request alone needs more than the budget.  bx_poll reports completion,
- * bx_take hands over the pair list (malloc'd) and releases the ticket.  Times
- * are seconds on the library's monotonic clock (bx_now). */
+ * overlap on the device.  bx_submit never blocks.  With the owner's option
+ * "submit_wait" = 1 (default) it queues the request and returns BX_EBUSY only
+ * when the request alone needs more than the budget; with "submit_wait" = 0
+ * it also returns BX_EBUSY, queueing nothing, unless the request can be
+ * admitted at once (no request queued, and an idle lane whose workspace for
+ * this request alone fits beside the other lanes').  bx_poll reports
+ * completion; bx_take hands over the pair list (malloc'd, sorted by (m, n))
+ * and releases the ticket (BX_EBUSY while the request runs); bx_take_timed
+ * also gives the submit and completion times, in seconds on the library's
+ * monotonic clock (bx_now; either pointer may be NULL). */
 int bx_serve_start(bx_ctx* ctx, uint64_t budget_bytes, int max_inflight);
 int bx_serve_stop(bx_ctx* ctx);
 int bx_submit(bx_ctx* ctx, uint64_t a, uint64_t b, uint32_t kinds, uint64_t* ticket);
 int bx_poll(bx_ctx* ctx, uint64_t ticket, int* done);
-int bx_take(bx_ctx* ctx, uint64_t ticket, bx_pair** out, size_t* count, double* t_submit, double* t_done);
+int bx_take(bx_ctx* ctx, uint64_t ticket, bx_pair** out, size_t* count);
+int bx_take_timed(bx_ctx* ctx, uint64_t ticket, bx_pair** out, size_t* count, double* t_submit, double* t_done);
 
 /* Admission record of the running server. */
 typedef struct {
@@ -229,7 +243,9 @@ int bx_get_stats(bx_ctx* ctx, bx_stats* out);
  *                  and no partition or join launch (default 8192; the pairs
  *                  are the same either way)
  *   "small_block"  threads per workgroup of that class: 256, 512 or 1024
- *                  (0 = 1024)  */
+ *                  (0 = 1024)
+ *   "submit_wait"  serving: 1 = bx_submit queues (default), 0 = bx_submit
+ *                  refuses with BX_EBUSY what cannot be admitted at once  */
 int bx_set_option(bx_ctx* ctx, const char* name, int64_t value);
 
 void bx_free(void* p);

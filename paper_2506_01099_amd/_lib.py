@@ -17,7 +17,7 @@ _NAMES = {BX_EINVAL: "BX_EINVAL", BX_ERANGE: "BX_ERANGE", BX_ENOMEM: "BX_ENOMEM"
 EXPORTS = [
     "bx_create", "bx_destroy", "bx_set_stream", "bx_radical_segment", "bx_radical_segment_dev",
     "bx_radical_segment_dev_noalloc", "bx_benelux_search", "bx_search_range", "bx_search_batch", "bx_serve_start", "bx_serve_stop",
-    "bx_submit", "bx_poll", "bx_take", "bx_serve_get_info", "bx_now", "bx_get_stats", "bx_set_option", "bx_free",
+    "bx_submit", "bx_poll", "bx_take", "bx_take_timed", "bx_serve_get_info", "bx_now", "bx_get_stats", "bx_set_option", "bx_free",
     "bx_autotune", "bx_load_tuning",
     "bx_last_error", "benelux_search", "radical_segment",
 ]
@@ -88,8 +88,9 @@ def load():
         "bx_serve_stop": ([vp], ctypes.c_int),
         "bx_submit": ([vp, u64, u64, u32, P64], ctypes.c_int),
         "bx_poll": ([vp, u64, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
-        "bx_take": ([vp, u64, PP, ctypes.POINTER(sz), ctypes.POINTER(ctypes.c_double),
-                     ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "bx_take": ([vp, u64, PP, ctypes.POINTER(sz)], ctypes.c_int),
+        "bx_take_timed": ([vp, u64, PP, ctypes.POINTER(sz), ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "bx_serve_get_info": ([vp, ctypes.POINTER(ServeInfo)], ctypes.c_int),
         "bx_now": ([], ctypes.c_double),
         "bx_autotune": ([vp, P64, P64, sz, ctypes.c_int, ctypes.c_char_p], ctypes.c_int),

@@ -160,9 +160,15 @@ class Server:
         """(pairs, t_submit, t_done) of a finished request."""
         p, c = ctypes.POINTER(Pair)(), ctypes.c_size_t(0)
         ts, td = ctypes.c_double(0), ctypes.c_double(0)
-        check(self._lib.bx_take(self.ctx._h, int(ticket), ctypes.byref(p), ctypes.byref(c), ctypes.byref(ts),
-                                ctypes.byref(td)))
+        check(self._lib.bx_take_timed(self.ctx._h, int(ticket), ctypes.byref(p), ctypes.byref(c), ctypes.byref(ts),
+                                      ctypes.byref(td)))
         return _pairs_from(p, c.value), ts.value, td.value
+
+    def take_pairs(self, ticket):
+        """The pair list of a finished request (bx_take)."""
+        p, c = ctypes.POINTER(Pair)(), ctypes.c_size_t(0)
+        check(self._lib.bx_take(self.ctx._h, int(ticket), ctypes.byref(p), ctypes.byref(c)))
+        return _pairs_from(p, c.value)
 
     def info(self):
         """Admission record: budget, peak and current workspace bytes, batches, waits."""

@@ -126,6 +126,7 @@ struct bx_ctx {
   int tile = kTileDefault;
   uint32_t small_max = kSmallMaxLen;  // longest query of the small class (0: class off)
   int small_block = 1024;             // threads of a small-class workgroup
+  int submit_wait = 1;                // 0: bx_submit refuses what cannot be admitted at once
   int graph_batch = 1;      // batched calls run as one captured HIP graph
   bool capturing = false;   // no event records while a stream capture is open
   hipGraphExec_t graph_exec = nullptr;
@@ -531,7 +532,10 @@ bool is_small(const bx_ctx* c, const Query& q) {
   return L >= 2 && L <= c->small_max;
 }
 
-void make_segs(const bx_ctx* c, Segs* s) {
+// Segments of every query; with small_class, the queries of the small-query
+// class take none and are listed in s->small instead (searches only: the
+// radical sieve segments every range).
+void make_segs(const bx_ctx* c, Segs* s, bool small_class) {
   s->prefix.assign(s->q.size() + 1, 0);
   s->small.clear();
   s->n_ints = 0;
@@ -540,7 +544,7 @@ void make_segs(const bx_ctx* c, Segs* s) {
   for (size_t i = 0; i < s->q.size(); ++i) {
     s->prefix[i] = acc;
     const uint64_t L = s->q[i].b > s->q[i].a ? s->q[i].b - s->q[i].a : 0;
-    if (is_small(c, s->q[i])) {
+    if (small_class && is_small(c, s->q[i])) {
       s->small.push_back(static_cast<uint32_t>(i));
       s->n_ints += L;
       continue;
@@ -1022,7 +1026,7 @@ int run_search(bx_ctx* c, Segs& s, int batch, uint32_t kinds, std::vector<OutPai
   if (rc != BX_OK) return rc;
   rc = mark_done(c, st);  // host-synchronous from here on: the call drains st
   if (rc != BX_OK) return rc;
-  make_segs(c, &s);
+  make_segs(c, &s, true);
   if (s.n_segs == 0 && s.small.empty()) return BX_OK;
   Job j;
   if ((rc = prepare_job(c, s, batch, kinds, st, &j)) != BX_OK) return rc;
@@ -1050,7 +1054,7 @@ int to_pairs(const std::vector<OutPair>& v, bx_pair** out, size_t* count) {
 int radicals_into(bx_ctx* c, uint64_t lo, uint64_t hi, uint64_t* dev_out, hipStream_t st, bool clear_flags = true) {
   Segs s;
   s.q.push_back(Query{lo, hi});
-  make_segs(c, &s);
+  make_segs(c, &s, false);
   if (s.n_segs == 0) return BX_OK;
   int rc;
   if ((rc = upload_segs(c, s, st)) != BX_OK) return rc;
@@ -1225,6 +1229,7 @@ struct bx_ctx::Server {
   // (what the batch's plan grows it to) or held between batches.  Their sum
   // never exceeds the budget.
   std::vector<uint64_t> held;
+  std::vector<char> busy;  // lane runs a batch
   uint64_t peak = 0, admitted = 0, batches = 0, mem_waits = 0, releases = 0;
   uint32_t max_batch = 0;
   bool stop = false;
@@ -1261,16 +1266,16 @@ void release_workspace(bx_ctx* c) {
 int batch_bytes(bx_ctx* c, const std::vector<Query>& q, bool released, uint64_t* bytes, uint32_t* passes = nullptr) {
   Segs s;
   s.q = q;
-  make_segs(c, &s);
+  make_segs(c, &s, true);
   *bytes = 0;
   if (passes) *passes = 1;
-  if (s.n_segs == 0) return BX_OK;
+  if (s.n_segs == 0 && s.small.empty()) return BX_OK;
   Job j;
   JobBufs nb;
   const int rc = plan_job(c, s, 1, BX_BOTH, &j, &nb);
   if (rc != BX_OK) return rc;
   *bytes = bytes_after(c, nb, released);
-  if (passes) *passes = j.plan.passes;
+  if (passes) *passes = std::max<uint32_t>(1, j.plan.passes);
   return BX_OK;
 }
 
@@ -1335,6 +1340,7 @@ void serve_worker(bx_ctx::Server* S, int lane) {
         continue;
       }
       S->held[lane] = reserve;
+      S->busy[lane] = 1;
       uint64_t total = 0;
       for (uint64_t h : S->held) total += h;
       S->peak = std::max(S->peak, total);
@@ -1384,6 +1390,7 @@ void serve_worker(bx_ctx::Server* S, int lane) {
       }
       // What the lane holds now (at most what was reserved for the batch).
       S->held[lane] = std::min(after, S->held[lane]);
+      S->busy[lane] = 0;
     }
     S->cv.notify_all();
   }
@@ -1493,6 +1500,8 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
   } else if (n == "group") {
     if (v != 0 && v != 1 && v != 2 && v != 4 && v != 8) return fail(BX_EINVAL, "group must be 0, 1, 2, 4 or 8");
     c->force_group = static_cast<int>(v);
+  } else if (n == "submit_wait") {
+    c->submit_wait = v != 0;
   } else if (n == "small_max") {
     if (v < 0 || v > static_cast<int64_t>(kSmallMaxLen)) return fail(BX_EINVAL, "small_max must be in [0, 8192]");
     c->small_max = static_cast<uint32_t>(v);
@@ -1714,6 +1723,7 @@ int bx_serve_start(bx_ctx* c, uint64_t budget_bytes, int max_inflight) {
   S->budget = budget_bytes ? budget_bytes : c->budget / 2;
   S->max_inflight = max_inflight;
   S->held.assign(max_inflight, 0);
+  S->busy.assign(max_inflight, 0);
   for (int i = 0; i < max_inflight; ++i) {
     bx_ctx* lane = nullptr;
     // A lane may plan with the whole budget; admission keeps the sum in it.
@@ -1780,6 +1790,23 @@ int bx_submit(bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds, uint64_t* ticke
   }
   {
     std::lock_guard<std::mutex> lk(S->mu);
+    if (!c->submit_wait) {
+      // Admitted now or refused: nothing queued ahead, and an idle lane whose
+      // workspace, rebuilt for this request alone (the lane releases its own
+      // first when it must), fits beside what the other lanes hold.
+      if (!S->queue.empty()) return fail(BX_EBUSY, "requests are queued (submit without waiting)");
+      bool room = false;
+      for (int l = 0; l < S->max_inflight && !room; ++l) {
+        if (S->busy[l]) continue;
+        uint64_t others = 0;
+        for (int k = 0; k < S->max_inflight; ++k)
+          if (k != l) others += S->held[k];
+        uint64_t bare = 0;
+        if (b <= a + 1 || (batch_bytes(S->lanes[l], {Query{a, b}}, true, &bare) == BX_OK && others + bare <= S->budget))
+          room = true;
+      }
+      if (!room) return fail(BX_EBUSY, "no lane can admit the request now (submit without waiting)");
+    }
     const uint64_t t = S->next_ticket++;
     auto r = std::make_unique<bx_ctx::Server::Req>();
     r->a = a;
@@ -1805,7 +1832,7 @@ int bx_poll(bx_ctx* c, uint64_t ticket, int* done) {
   return BX_OK;
 }
 
-int bx_take(bx_ctx* c, uint64_t ticket, bx_pair** out, size_t* count, double* t_submit, double* t_done) {
+int bx_take_timed(bx_ctx* c, uint64_t ticket, bx_pair** out, size_t* count, double* t_submit, double* t_done) {
   if (!c || !out || !count) return fail(BX_EINVAL, "NULL argument");
   if (!c->server) return fail(BX_EINVAL, "server not started");
   auto* S = c->server.get();
@@ -1822,6 +1849,10 @@ int bx_take(bx_ctx* c, uint64_t ticket, bx_pair** out, size_t* count, double* t_
   if (t_done) *t_done = r->t_done;
   if (r->rc != BX_OK) return fail(r->rc, "request failed");
   return to_pairs(r->pairs, out, count);
+}
+
+int bx_take(bx_ctx* c, uint64_t ticket, bx_pair** out, size_t* count) {
+  return bx_take_timed(c, ticket, out, count, nullptr, nullptr);
 }
 
 int bx_serve_get_info(bx_ctx* c, bx_serve_info* out) {

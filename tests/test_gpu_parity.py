@@ -787,6 +787,48 @@ def test_served_request_beyond_budget_is_refused(ctx):
         srv.stop()
 
 
+def test_served_submit_without_waiting(ctx):
+    """With option submit_wait = 0 a request is admitted at once or refused with BX_EBUSY,
+    queueing nothing: an idle server admits it; while the one lane runs a burst, it is
+    refused.  Admitted requests return Theorem 1's lists, through bx_take (no times)."""
+    import time
+
+    from paper_2506_01099_amd import BxError, Server
+
+    srv = Server(ctx, max_inflight=1)
+    ctx.set_option("submit_wait", 0)
+    try:
+        t = srv.submit(1, 1 << 16)  # idle lane, empty queue: admitted
+        while not srv.poll(t):
+            time.sleep(0.001)
+        assert srv.take_pairs(t) == oracle.search_range(1, 1 << 16)
+        ctx.set_option("submit_wait", 1)
+        burst = [srv.submit(1, 1 << 27) for _ in range(6)]
+        ctx.set_option("submit_wait", 0)
+        refused, extra = 0, []
+        for _ in range(50):
+            try:
+                extra.append(srv.submit(1, 1 << 20))
+            except BxError as e:
+                assert e.code == -5  # BX_EBUSY
+                refused += 1
+        assert refused > 0
+        for t in burst:
+            while not srv.poll(t):
+                time.sleep(0.001)
+            assert srv.take_pairs(t) == theorem1_pairs((1 << 27) - 1)
+        for t in extra:
+            while not srv.poll(t):
+                time.sleep(0.001)
+            assert srv.take_pairs(t) == theorem1_pairs((1 << 20) - 1)
+        with pytest.raises(BxError) as ei:
+            srv.take_pairs(burst[0])  # already taken
+        assert ei.value.code == -1
+    finally:
+        ctx.set_option("submit_wait", 1)
+        srv.stop()
+
+
 def test_served_kinds_and_lane_options(ctx):
     """Requests with different kinds masks share batches; the lanes run with the owner's
     options at serve start (here the sort join)."""
