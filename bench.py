@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the sort-join ablation run")
     ap.add_argument("--no-paper-schedule", action="store_true",
-                    help="skip Algorithm 3's chunk schedule at 2^32 (the paper's design, a baseline)")
+                    help="skip the paper's own designs at 2^32 (Algorithm 3's chunk schedule, Algorithm 2's whole-range sort)")
     ap.add_argument("--calib", action="store_true",
                     help="first copy 4 GiB with a plain copy kernel (reference for HBM counters)")
     ap.add_argument("--parse-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -399,6 +399,26 @@ def main():
                                        "radicals_ms": st_a3["kernel_ms"]["radicals"],
                                        "insert_probe_ms": st_a3["kernel_ms"]["join"],
                                        "hash_partitioned_seconds": t_hash, "pairs": len(p_a3)}
+        # Algorithm 2 (the whole range's list sorted once, runs of equal keys) on the same range.
+        log("whole-range sort (Algorithm 2) at 2^32 ...")
+        bx.set_option("schedule", 2)
+        try:
+            bx.search(N32)  # warm: allocates the list
+            t0 = time.perf_counter()
+            p_a2 = bx.search(N32)
+            t_a2 = time.perf_counter() - t0
+            st_a2 = bx.stats()
+        finally:
+            bx.set_option("schedule", 0)
+        if p_a2 != p_hash:
+            raise SystemExit("pair lists differ between Algorithm 2 and the hash-partitioned passes")
+        line["whole_range_sort_2p32"] = {"seconds": t_a2, "integers_per_s": N32 / t_a2, "entries": st_a2["entries"],
+                                         "sort_passes": st_a2["passes"],
+                                         "radicals_ms": st_a2["kernel_ms"]["radicals"],
+                                         "keys_ms": st_a2["kernel_ms"]["sieve"],
+                                         "sort_ms": st_a2["kernel_ms"]["partition"],
+                                         "runs_ms": st_a2["kernel_ms"]["join"],
+                                         "hash_partitioned_seconds": t_hash, "pairs": len(p_a2)}
     if not args.no_batched or args.served > 0:
         if os.path.exists(args.tuning):
             bx.load_tuning(args.tuning)

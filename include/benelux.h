@@ -245,7 +245,19 @@ int bx_get_stats(bx_ctx* ctx, bx_stats* out);
  *   "small_block"  threads per workgroup of that class: 256, 512 or 1024
  *                  (0 = 1024)
  *   "submit_wait"  serving: 1 = bx_submit queues (default), 0 = bx_submit
- *                  refuses with BX_EBUSY what cannot be admitted at once  */
+ *                  refuses with BX_EBUSY what cannot be admitted at once
+ *   "schedule"     single-range searches (bx_benelux_search, bx_search_range):
+ *                  0 = hash-partitioned passes (default); 1 = Algorithm 3's
+ *                  schedule (chunks of s values overlapping by one, each
+ *                  inserted into an open-addressing table of 4s slots in device
+ *                  memory, every earlier chunk sieved again and probed); 2 =
+ *                  Algorithm 2 (the list of (S_n, n) over the whole range,
+ *                  radix-sorted by a fingerprint of S_n, every pair inside a
+ *                  run of equal keys verified; 32 bytes of device memory per
+ *                  kept integer, BX_ENOMEM beyond the budget).  Same pair lists;
+ *                  baselines of the paper's own designs.  Batched calls and
+ *                  serving always use 0.
+ *   "a3_chunk_log2" log2 of Algorithm 3's chunk size s (10 .. 27; 0 = 27)  */
 int bx_set_option(bx_ctx* ctx, const char* name, int64_t value);
 
 void bx_free(void* p);

@@ -21,6 +21,7 @@
 #include <thread>
 #include <vector>
 
+#include "bx_alg2.h"
 #include "bx_alg3.h"
 #include "bx_kernels.h"
 #include "bx_small.h"
@@ -114,11 +115,12 @@ struct bx_ctx {
   PrimePow* d_pp = nullptr;
   DenseTab* d_dense[2] = {nullptr, nullptr};
   DevBuf l1, l2, cnt1, cnt2, cand, out, flags, spill, queries, segpref, rad, acc, a3tab, smallq;
+  DevBuf a2k[2], a2v[2], a2hist, a2offs, a2tot;  // Algorithm 2: list (double-buffered), sort counts
   int force_passes = 0, timing = 1, force_b1 = -1, force_b2 = -1, force_group = 0;
   int prune = 1;            // drop x that cannot be a pair member before the join
   int join_sort = 0;        // 1: the sort join per partition (ablation of the hash join)
   uint32_t third_off = 2;   // offset d of the third condition rad(m + d) = rad(n + d); 2 is Erdős's
-  int schedule = 0;         // 0: hash-partitioned passes, 1: Algorithm 3's chunk schedule (a baseline)
+  int schedule = 0;         // 0: hash-partitioned passes, 1: Algorithm 3's chunk schedule, 2: Algorithm 2's sort (baselines)
   uint32_t a3_log2 = 27;    // Algorithm 3's chunk size s = 2^a3_log2 (a table of 4s slots)
   // Fingerprint bits kept: all 53 in use; tests keep the top 11 (the
   // partition bits) and a few low ones to make different sets collide.
@@ -1147,6 +1149,122 @@ int run_alg3(bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds, std::vector<OutP
   return collect_pairs(c, fl, st, result);
 }
 
+// Algorithm 2 over [a, b): radicals in chunks, one list entry (fingerprint of
+// S_n, n) per kept n, the list radix-sorted by fingerprint (seven passes of 8
+// bits cover the 53), every pair inside each run of equal keys a candidate,
+// verified as in the passes.  The list needs 32 bytes per kept integer (keys
+// and values, double-buffered): a baseline for ranges that fit in memory.
+int run_alg2(bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds, std::vector<OutPair>* result) {
+  hipStream_t st = c->stream;
+  result->clear();
+  int rc;
+  if ((rc = order_after_last(c, st)) != BX_OK) return rc;
+  if ((rc = mark_done(c, st)) != BX_OK) return rc;
+  Segs s;
+  s.q.push_back(Query{a, b});
+  make_segs(c, &s, false);
+  const uint64_t cap = s.n_keys + 64;  // bound on the kept integers
+  const uint64_t chunk = 1ull << 27;
+  const uint64_t n_tiles_max = (cap + kRsTile - 1) / kRsTile, m_max = 256 * n_tiles_max;
+  const uint64_t nt_max = (m_max + kScanTile - 1) / kScanTile;
+  const uint64_t need = 4 * cap * 8 + m_max * 12 + nt_max * 8 + (std::min(chunk, b - a) + 1) * 8;
+  if (need + fixed_bytes(c, 0) > c->budget)
+    return fail(BX_ENOMEM, "Algorithm 2 needs " + std::to_string(need) + " device bytes for its list, budget " +
+                               std::to_string(c->budget));
+  for (int k = 0; k < 2; ++k) {
+    if ((rc = ensure(c, c->a2k[k], cap * 8)) != BX_OK) return rc;
+    if ((rc = ensure(c, c->a2v[k], cap * 8)) != BX_OK) return rc;
+  }
+  if ((rc = ensure(c, c->a2hist, m_max * 4)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->a2offs, m_max * 8)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->a2tot, nt_max * 8)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->rad, (std::min(chunk, b - a) + 1) * sizeof(uint64_t))) != BX_OK) return rc;
+  if ((rc = ensure(c, c->cand, kCandCap * sizeof(Cand))) != BX_OK) return rc;
+  if ((rc = ensure(c, c->out, kCandCap * sizeof(OutPair))) != BX_OK) return rc;
+  if ((rc = ensure(c, c->flags, kFlagCount * 4)) != BX_OK) return rc;
+  if ((rc = ensure(c, c->acc, kAccCount * sizeof(unsigned long long))) != BX_OK) return rc;
+  if ((rc = fill_u32(c, c->flags.p, kFlagCount, 0, st)) != BX_OK) return rc;
+  if ((rc = fill_u32(c, c->acc.p, 2 * kAccCount, 0, st)) != BX_OK) return rc;
+  uint64_t* rad = static_cast<uint64_t*>(c->rad.p);
+  A2KeyParams K;
+  K.rad = rad;
+  K.qb = b;
+  K.prune = c->prune;
+  K.fp_mask = c->fp_mask;
+  K.keys = static_cast<uint64_t*>(c->a2k[0].p);
+  K.vals = static_cast<uint64_t*>(c->a2v[0].p);
+  K.cap = cap;
+  K.n_out = static_cast<unsigned long long*>(c->acc.p) + kAccEntries;
+  K.flags = static_cast<uint32_t*>(c->flags.p);
+  for (uint64_t c0 = a; c0 < b; c0 += chunk) {
+    const uint64_t cnt = std::min(chunk, b - c0);
+    if ((rc = radicals_into(c, c0, c0 + cnt + 1, rad, st, false)) != BX_OK) return rc;
+    K.c0 = c0;
+    K.count = static_cast<uint32_t>(cnt);
+    {
+      LaunchTimer t(c, K_SIEVE, st);
+      hipLaunchKernelGGL((k_a2_keys<256>), dim3(static_cast<uint32_t>(std::min<uint64_t>((cnt + 255) / 256, 8192))),
+                         dim3(256), 0, st, K);
+    }
+    BX_HIP(hipGetLastError());
+  }
+  unsigned long long acc[kAccCount] = {0, 0};
+  BX_HIP(hipMemcpyAsync(acc, c->acc.p, sizeof(acc), hipMemcpyDeviceToHost, st));
+  BX_HIP(hipStreamSynchronize(st));
+  const uint64_t n = acc[kAccEntries];
+  if (n > cap) return fail(BX_EINTERNAL, "Algorithm 2: more kept integers than the bound");
+  c->stats.integers = b - a;
+  c->stats.entries = n;
+  // Radix sort of (key, value) by key, least significant digit first.
+  const uint64_t n_tiles = (n + kRsTile - 1) / kRsTile, m = 256 * n_tiles;
+  const uint64_t nt = (m + kScanTile - 1) / kScanTile;
+  int cur = 0;
+  for (uint32_t shift = 0; shift < kFpBits && n > 1; shift += 8) {
+    const uint64_t* ki = static_cast<const uint64_t*>(c->a2k[cur].p);
+    const uint64_t* vi = static_cast<const uint64_t*>(c->a2v[cur].p);
+    uint32_t* hist = static_cast<uint32_t*>(c->a2hist.p);
+    uint64_t* offs = static_cast<uint64_t*>(c->a2offs.p);
+    uint64_t* tot = static_cast<uint64_t*>(c->a2tot.p);
+    {
+      LaunchTimer t(c, K_PART, st);
+      hipLaunchKernelGGL(k_rs_hist, dim3(static_cast<uint32_t>(n_tiles)), dim3(kRsBlock), 0, st, ki, n, shift, hist,
+                         n_tiles);
+      hipLaunchKernelGGL(k_scan_tiles, dim3(static_cast<uint32_t>(nt)), dim3(kScanBlock), 0, st, hist, m, offs, tot);
+      hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanBlock), 0, st, tot, nt);
+      hipLaunchKernelGGL(k_scan_add, dim3(static_cast<uint32_t>(nt)), dim3(kScanBlock), 0, st, offs, m, tot);
+      hipLaunchKernelGGL(k_rs_scatter, dim3(static_cast<uint32_t>(n_tiles)), dim3(kRsBlock), 0, st, ki, vi, n, shift,
+                         offs, n_tiles, static_cast<uint64_t*>(c->a2k[cur ^ 1].p),
+                         static_cast<uint64_t*>(c->a2v[cur ^ 1].p));
+    }
+    BX_HIP(hipGetLastError());
+    cur ^= 1;
+    c->stats.passes++;
+  }
+  {
+    LaunchTimer t(c, K_JOIN, st);
+    hipLaunchKernelGGL(k_a2_runs, dim3(static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 8192)))),
+                       dim3(256), 0, st, static_cast<const uint64_t*>(c->a2k[cur].p),
+                       static_cast<const uint64_t*>(c->a2v[cur].p), n, static_cast<Cand*>(c->cand.p), kCandCap,
+                       static_cast<uint32_t*>(c->flags.p));
+  }
+  BX_HIP(hipGetLastError());
+  uint32_t fl[kFlagCount];
+  if ((rc = read_flags(c, fl, st)) != BX_OK) return rc;
+  if (fl[kFlagSpillOverflow]) return fail(BX_EINTERNAL, "sparse-hit overflow in the radical sieve");
+  if (fl[kFlagL1Overflow]) return fail(BX_EINTERNAL, "Algorithm 2: list overflow");
+  if (fl[kFlagCand] > kCandCap) return fail(BX_EINTERNAL, "candidate buffer overflow");
+  if (fl[kFlagCand] > 0) {
+    Job j;
+    j.batch = 0;
+    j.kinds = kinds;
+    if ((rc = enqueue_verify(c, j, std::min<uint32_t>(fl[kFlagCand], kVerifyGrid), st)) != BX_OK) return rc;
+    if ((rc = read_flags(c, fl, st)) != BX_OK) return rc;
+  }
+  rc = collect_pairs(c, fl, st, result);
+  c->stats.joined = n;
+  return rc;
+}
+
 // Scratch of bx_radical_segment_dev_noalloc: the counter words, the one-query
 // table and the sparse-hit spill of up to kNaGrid sieve workgroups, in one
 // fixed device array (every device the library runs on holds its own copy
@@ -1437,7 +1555,8 @@ void bx_destroy(bx_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (DevBuf* b : {&c->l1, &c->l2, &c->cnt1, &c->cnt2, &c->cand, &c->out, &c->flags, &c->spill, &c->queries,
-                    &c->segpref, &c->rad, &c->acc, &c->a3tab, &c->smallq})
+                    &c->segpref, &c->rad, &c->acc, &c->a3tab, &c->smallq, &c->a2k[0], &c->a2k[1], &c->a2v[0],
+                    &c->a2v[1], &c->a2hist, &c->a2offs, &c->a2tot})
     free_buf(*b);
   if (c->d_primes) (void)hipFree(c->d_primes);
   if (c->d_pp) (void)hipFree(c->d_pp);
@@ -1476,7 +1595,8 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
     if (v != 0 && v != kTileSmall && v != kTileLarge) return fail(BX_EINVAL, "tile must be 0, 2048 or 8192");
     c->tile = v == 0 ? kTileDefault : static_cast<int>(v);
   } else if (n == "schedule") {
-    if (v != 0 && v != 1) return fail(BX_EINVAL, "schedule must be 0 (hash-partitioned passes) or 1 (Algorithm 3)");
+    if (v < 0 || v > 2)
+      return fail(BX_EINVAL, "schedule must be 0 (hash-partitioned passes), 1 (Algorithm 3) or 2 (Algorithm 2)");
     c->schedule = static_cast<int>(v);
   } else if (n == "a3_chunk_log2") {
     if (v == 0) v = 27;
@@ -1661,7 +1781,9 @@ int bx_search_range(bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds, bx_pair**
   Segs s;
   s.q.push_back(Query{a, b});
   std::vector<OutPair> res;
-  rc = c->schedule == 1 ? run_alg3(c, a, b, kinds, &res) : run_search(c, s, 0, kinds, &res, false);
+  rc = c->schedule == 1   ? run_alg3(c, a, b, kinds, &res)
+       : c->schedule == 2 ? run_alg2(c, a, b, kinds, &res)
+                          : run_search(c, s, 0, kinds, &res, false);
   (void)hipStreamSynchronize(c->stream);
   collect_timings(c);
   c->stats.total_ms = (now_s() - t0) * 1e3;

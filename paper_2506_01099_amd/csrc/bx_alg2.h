@@ -1,0 +1,257 @@
+// Algorithm 2 of the paper as HIP kernels (a baseline beside the hash-
+// partitioned passes): the radicals of the whole range, one list entry
+// (S_n, n) per integer n, the list sorted by S_n, and every run of equal keys
+// reported.  The sort key is the 53-bit fingerprint of the set
+// S_n = {rad(n), rad(n + 1)} (equal sets have equal fingerprints; different
+// sets that share one are dropped by the verification, which recomputes the
+// radicals).  Where the paper compares neighbours only, every pair inside a
+// run is reported, so groups of three or more equal sets give all their pairs.
+//
+//   k_a2_keys      fingerprints of the kept integers of one chunk of radicals,
+//                  compacted into the list (one atomic per wave).
+//   k_rs_hist      least-significant-digit radix sort, 8 bits per pass: digit
+//   k_scan_*       counts per tile, an exclusive scan over (digit, tile), and
+//   k_rs_scatter   a stable scatter (lanes of a wave rank equal digits by
+//                  ballots; waves keep running counts in LDS).
+//   k_a2_runs      every pair inside each run of equal keys of the sorted list.
+#pragma once
+#include "bx_kernels.h"
+
+namespace bx {
+
+constexpr int kRsBlock = 256;                 // threads of a sort workgroup (4 waves)
+constexpr int kRsIter = 16;                   // items per thread
+constexpr int kRsTile = kRsBlock * kRsIter;   // items per workgroup
+constexpr int kScanBlock = 1024;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+struct A2KeyParams {
+  const uint64_t* rad;  // rad[t] = rad(c0 + t), t in [0, count]
+  uint64_t c0;
+  uint32_t count;
+  uint64_t qb;          // end of the range (member test)
+  uint32_t prune;
+  uint64_t fp_mask;
+  uint64_t* keys;
+  uint64_t* vals;
+  uint64_t cap;
+  unsigned long long* n_out;  // entries written so far (all chunks)
+  uint32_t* flags;
+};
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_a2_keys(A2KeyParams P) {
+  const uint64_t below = (1ull << __lane_id()) - 1ull;
+  for (uint64_t t0 = static_cast<uint64_t>(blockIdx.x) * BLOCK; t0 < P.count; t0 += static_cast<uint64_t>(gridDim.x) * BLOCK) {
+    const uint64_t t = t0 + threadIdx.x;
+    bool keep = false;
+    uint64_t fp = 0, x = P.c0 + t;
+    if (t < P.count) {
+      const uint64_t r0 = P.rad[t], r1 = P.rad[t + 1];
+      keep = !P.prune || may_pair(x, r0, r1, P.qb);
+      fp = (key64(r0 < r1 ? r0 : r1, r0 < r1 ? r1 : r0, 0) >> 11) & P.fp_mask;
+    }
+    const uint64_t m = __ballot(keep);
+    if (m == 0) continue;
+    unsigned long long base = 0;
+    if (__lane_id() == 0) base = atomicAdd(P.n_out, static_cast<unsigned long long>(__popcll(m)));
+    base = __shfl(base, 0, 64);
+    if (keep) {
+      const uint64_t k = base + __popcll(m & below);
+      if (k < P.cap) {
+        P.keys[k] = fp;
+        P.vals[k] = x;
+      } else {
+        atomicOr(&P.flags[kFlagL1Overflow], 1u);
+      }
+    }
+  }
+}
+
+// Digit counts of tile b: hist[d * n_tiles + b] (digit-major, so that the
+// exclusive scan gives every (digit, tile) its first output position).
+__global__ __launch_bounds__(kRsBlock) void k_rs_hist(const uint64_t* keys, uint64_t n, uint32_t shift, uint32_t* hist,
+                                                     uint64_t n_tiles) {
+  __shared__ uint32_t h[256];
+  const int tid = threadIdx.x;
+  h[tid] = 0;
+  __syncthreads();
+  const uint64_t base = blockIdx.x * static_cast<uint64_t>(kRsTile);
+#pragma unroll
+  for (int it = 0; it < kRsIter; ++it) {
+    const uint64_t i = base + it * kRsBlock + tid;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[tid * n_tiles + blockIdx.x] = h[tid];
+}
+
+// Exclusive scan of m 32-bit counts into 64-bit offsets, in three steps:
+// tiles of kScanTile (local scan, tile totals), the totals, the carry-in.
+__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const uint32_t* in, uint64_t m, uint64_t* out,
+                                                          uint64_t* totals) {
+  __shared__ uint64_t wsum[kScanBlock / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const uint64_t base = blockIdx.x * static_cast<uint64_t>(kScanTile) + static_cast<uint64_t>(tid) * kScanItems;
+  uint64_t v[kScanItems], s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = base + k < m ? in[base + k] : 0u;
+    s += v[k];
+  }
+  uint64_t x = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wid] = x;
+  __syncthreads();
+  if (wid == 0) {
+    uint64_t w = lane < kScanBlock / 64 ? wsum[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint64_t y = __shfl_up(w, o, 64);
+      if (lane >= o) w += y;
+    }
+    if (lane < kScanBlock / 64) wsum[lane] = w;
+  }
+  __syncthreads();
+  uint64_t run = (wid ? wsum[wid - 1] : 0) + x - s;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < m) out[base + k] = run;
+    run += v[k];
+  }
+  if (tid == kScanBlock - 1) totals[blockIdx.x] = wsum[kScanBlock / 64 - 1];
+}
+
+// One workgroup: exclusive scan of the nt tile totals, in place.
+__global__ __launch_bounds__(kScanBlock) void k_scan_totals(uint64_t* totals, uint64_t nt) {
+  __shared__ uint64_t wsum[kScanBlock / 64];
+  __shared__ uint64_t carry_s;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (tid == 0) carry_s = 0;
+  __syncthreads();
+  for (uint64_t b0 = 0; b0 < nt; b0 += kScanBlock) {
+    const uint64_t i = b0 + tid;
+    const uint64_t v = i < nt ? totals[i] : 0;
+    uint64_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint64_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+      uint64_t w = lane < kScanBlock / 64 ? wsum[lane] : 0;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(w, o, 64);
+        if (lane >= o) w += y;
+      }
+      if (lane < kScanBlock / 64) wsum[lane] = w;
+    }
+    __syncthreads();
+    const uint64_t carry = carry_s;
+    if (i < nt) totals[i] = carry + (wid ? wsum[wid - 1] : 0) + x - v;
+    __syncthreads();
+    if (tid == 0) carry_s = carry + wsum[kScanBlock / 64 - 1];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_add(uint64_t* out, uint64_t m, const uint64_t* totals) {
+  const uint64_t base = blockIdx.x * static_cast<uint64_t>(kScanTile);
+  const uint64_t add = totals[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t i = base + k * kScanBlock + threadIdx.x;
+    if (i < m) out[i] += add;
+  }
+}
+
+// Stable scatter of tile b by the digit at `shift`.  Wave w owns the items
+// [w * 1024, (w + 1) * 1024) of the tile, 64 consecutive items per step, so
+// index order is (wave, step, lane) order.  Lanes holding the same digit find
+// each other with eight ballots; the group's first lane advances the wave's
+// running count of that digit.  The digit's position is then the scanned
+// offset of (digit, tile), plus the counts of the earlier waves, plus the rank.
+__global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint64_t* keys_in, const uint64_t* vals_in, uint64_t n,
+                                                        uint32_t shift, const uint64_t* offs, uint64_t n_tiles,
+                                                        uint64_t* keys_out, uint64_t* vals_out) {
+  constexpr int W = kRsBlock / 64;
+  __shared__ uint32_t wc[W][256];
+  __shared__ uint64_t dofs[W][256];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int k = 0; k < W; ++k) wc[k][tid] = 0;
+  __syncthreads();
+  const uint64_t below = (1ull << lane) - 1ull;
+  const uint64_t base = blockIdx.x * static_cast<uint64_t>(kRsTile) + static_cast<uint64_t>(w) * (kRsTile / W);
+  uint64_t key[kRsIter], val[kRsIter];
+  uint32_t rank[kRsIter];
+#pragma unroll
+  for (int it = 0; it < kRsIter; ++it) {
+    const uint64_t i = base + it * 64 + lane;
+    const bool ok = i < n;
+    key[it] = ok ? keys_in[i] : 0;
+    val[it] = ok ? vals_in[i] : 0;
+    const uint32_t d = static_cast<uint32_t>(key[it] >> shift) & 255u;
+    uint64_t same = __ballot(ok);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const uint64_t bb = __ballot((d >> bit) & 1u);
+      same &= ((d >> bit) & 1u) ? bb : ~bb;
+    }
+    const uint32_t c0 = wc[w][d];
+    if (ok && (same & below) == 0) wc[w][d] = c0 + static_cast<uint32_t>(__popcll(same));
+    rank[it] = c0 + static_cast<uint32_t>(__popcll(same & below));
+  }
+  __syncthreads();
+  {
+    const uint32_t d = tid;  // kRsBlock == 256 digits
+    uint64_t s = offs[static_cast<uint64_t>(d) * n_tiles + blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      dofs[k][d] = s;
+      s += wc[k][d];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kRsIter; ++it) {
+    const uint64_t i = base + it * 64 + lane;
+    if (i < n) {
+      const uint64_t pos = dofs[w][static_cast<uint32_t>(key[it] >> shift) & 255u] + rank[it];
+      keys_out[pos] = key[it];
+      vals_out[pos] = val[it];
+    }
+  }
+}
+
+// Every pair inside each run of equal keys: the thread at the run's first
+// entry reports them.
+__global__ __launch_bounds__(256) void k_a2_runs(const uint64_t* keys, const uint64_t* vals, uint64_t n, Cand* cand,
+                                                uint32_t cand_cap, uint32_t* flags) {
+  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i + 1 < n; i += gridDim.x * 256ull) {
+    const uint64_t k = keys[i];
+    if (keys[i + 1] != k || (i > 0 && keys[i - 1] == k)) continue;
+    uint64_t j = i + 1;
+    while (j < n && keys[j] == k) ++j;
+    for (uint64_t u = i; u < j; ++u)
+      for (uint64_t v = u + 1; v < j; ++v) {
+        const uint32_t slot = atomicAdd(&flags[kFlagCand], 1u);
+        if (slot < cand_cap) {
+          Cand c;
+          c.a = make_entry(vals[u], k);
+          c.b = make_entry(vals[v], k);
+          cand[slot] = c;
+        }
+      }
+  }
+}
+
+}  // namespace bx

@@ -227,6 +227,59 @@ def test_paper_schedule_2_32_theorem1(ctx):
     say(f"  {st['total_ms']:.0f} ms")
 
 
+@pytest.mark.parametrize("N,prune", [(1 << 16, 1), (1 << 20, 1), ((1 << 20) + 12345, 1), (1 << 20, 0), (4374, 1)])
+def test_whole_range_sort_matches_oracle(ctx, N, prune):
+    """Algorithm 2: the whole range's list sorted by key, every run of equal keys reported."""
+    say(f"Algorithm 2 at N={N}, member test {prune}")
+    ctx.set_option("schedule", 2)
+    ctx.set_option("prune", prune)
+    try:
+        got = ctx.search(N)
+        st = ctx.stats()
+        rng = ctx.search_range(35, 4375)
+    finally:
+        ctx.set_option("schedule", 0)
+        ctx.set_option("prune", 1)
+    assert got == oracle.search(N)
+    assert rng == oracle.search_range(35, 4375)
+    assert st["passes"] == 7  # 8-bit digits over the 53-bit fingerprint
+    if not prune:
+        assert st["entries"] == N
+
+
+def test_whole_range_sort_candidates_exact(ctx):
+    """Every pair of equal (masked) fingerprints in the sorted list is a candidate: with
+    11 + 13 fingerprint bits kept the count is known exactly from the oracle's radicals."""
+    N, fp_bits = 1 << 24, 13
+    ctx.set_option("schedule", 2)
+    ctx.set_option("fp_bits", fp_bits)
+    try:
+        got = ctx.search(N)
+        st = ctx.stats()
+    finally:
+        ctx.set_option("schedule", 0)
+        ctx.set_option("fp_bits", 0)
+    assert got == oracle.search(N)
+    keys, n_kept = join_model.group_keys(oracle.radicals(1, N + 2), 1, N + 1, 0, 0, 1, fp_bits)
+    want = join_model.candidates(keys)
+    assert st["entries"] == n_kept
+    assert 10**4 < want < 10**6
+    assert st["candidates"] == want
+    assert st["candidates"] == st["pairs"] + st["false_candidates"]
+
+
+def test_whole_range_sort_2_32_theorem1(ctx):
+    say("Algorithm 2 up to 2^32")
+    ctx.set_option("schedule", 2)
+    try:
+        got = ctx.search(1 << 32)
+        st = ctx.stats()
+    finally:
+        ctx.set_option("schedule", 0)
+    assert got == theorem1_pairs(1 << 32)
+    say(f"  {st['total_ms']:.0f} ms, {st['entries']} entries")
+
+
 def test_sort_join_chunks_collisions_and_batch(ctx):
     """Partitions of several LDS chunks (one first- and one second-level bit), colliding
     fingerprints and a batch, all through the sort join."""
