@@ -1203,8 +1203,9 @@ int run_alg2(bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds, std::vector<OutP
     K.count = static_cast<uint32_t>(cnt);
     {
       LaunchTimer t(c, K_SIEVE, st);
-      hipLaunchKernelGGL((k_a2_keys<256>), dim3(static_cast<uint32_t>(std::min<uint64_t>((cnt + 255) / 256, 8192))),
-                         dim3(256), 0, st, K);
+      const uint64_t tiles = (cnt + 256 * kA2Items - 1) / (256 * kA2Items);
+      hipLaunchKernelGGL((k_a2_keys<256>), dim3(static_cast<uint32_t>(std::min<uint64_t>(tiles, 4096))), dim3(256), 0,
+                         st, K);
     }
     BX_HIP(hipGetLastError());
   }

@@ -8,7 +8,7 @@
 // run is reported, so groups of three or more equal sets give all their pairs.
 //
 //   k_a2_keys      fingerprints of the kept integers of one chunk of radicals,
-//                  compacted into the list (one atomic per wave).
+//                  compacted into the list (one atomic per tile of 4096).
 //   k_rs_hist      least-significant-digit radix sort, 8 bits per pass: digit
 //   k_scan_*       counts per tile, an exclusive scan over (digit, tile), and
 //   k_rs_scatter   a stable scatter (lanes of a wave rank equal digits by
@@ -40,30 +40,48 @@ struct A2KeyParams {
   uint32_t* flags;
 };
 
+// One tile of BLOCK * kA2Items consecutive integers per step: each thread
+// tests its kA2Items integers (strided by BLOCK, so that the radical loads
+// coalesce), a block scan ranks the kept ones, and one atomic per tile
+// reserves their list entries (one counter shared by the whole grid, so the
+// reservations must be few).
+constexpr int kA2Items = 16;
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_a2_keys(A2KeyParams P) {
-  const uint64_t below = (1ull << __lane_id()) - 1ull;
-  for (uint64_t t0 = static_cast<uint64_t>(blockIdx.x) * BLOCK; t0 < P.count; t0 += static_cast<uint64_t>(gridDim.x) * BLOCK) {
-    const uint64_t t = t0 + threadIdx.x;
-    bool keep = false;
-    uint64_t fp = 0, x = P.c0 + t;
-    if (t < P.count) {
-      const uint64_t r0 = P.rad[t], r1 = P.rad[t + 1];
-      keep = !P.prune || may_pair(x, r0, r1, P.qb);
-      fp = (key64(r0 < r1 ? r0 : r1, r0 < r1 ? r1 : r0, 0) >> 11) & P.fp_mask;
+  __shared__ uint32_t wsum[BLOCK / 64];
+  __shared__ unsigned long long base_s;
+  constexpr uint64_t kTileN = static_cast<uint64_t>(BLOCK) * kA2Items;
+  for (uint64_t t0 = blockIdx.x * kTileN; t0 < P.count; t0 += gridDim.x * kTileN) {
+    uint32_t keep = 0;
+    uint64_t fp[kA2Items];
+#pragma unroll
+    for (int k = 0; k < kA2Items; ++k) {
+      const uint64_t t = t0 + static_cast<uint64_t>(k) * BLOCK + threadIdx.x;
+      fp[k] = 0;
+      if (t < P.count) {
+        const uint64_t r0 = P.rad[t], r1 = P.rad[t + 1];
+        if (!P.prune || may_pair(P.c0 + t, r0, r1, P.qb)) {
+          keep |= 1u << k;
+          fp[k] = (key64(r0 < r1 ? r0 : r1, r0 < r1 ? r1 : r0, 0) >> 11) & P.fp_mask;
+        }
+      }
     }
-    const uint64_t m = __ballot(keep);
-    if (m == 0) continue;
-    unsigned long long base = 0;
-    if (__lane_id() == 0) base = atomicAdd(P.n_out, static_cast<unsigned long long>(__popcll(m)));
-    base = __shfl(base, 0, 64);
-    if (keep) {
-      const uint64_t k = base + __popcll(m & below);
-      if (k < P.cap) {
-        P.keys[k] = fp;
-        P.vals[k] = x;
-      } else {
-        atomicOr(&P.flags[kFlagL1Overflow], 1u);
+    uint32_t total = 0;
+    const uint32_t pre = block_exclusive_scan<BLOCK>(static_cast<uint32_t>(__popc(keep)), wsum, &total);
+    if (threadIdx.x == 0) base_s = total ? atomicAdd(P.n_out, static_cast<unsigned long long>(total)) : 0ull;
+    __syncthreads();
+    uint64_t k_out = base_s + pre;
+    __syncthreads();  // base_s and wsum are rewritten by the next tile
+#pragma unroll
+    for (int k = 0; k < kA2Items; ++k) {
+      if ((keep >> k) & 1u) {
+        if (k_out < P.cap) {
+          P.keys[k_out] = fp[k];
+          P.vals[k_out] = P.c0 + t0 + static_cast<uint64_t>(k) * BLOCK + threadIdx.x;
+        } else {
+          atomicOr(&P.flags[kFlagL1Overflow], 1u);
+        }
+        ++k_out;
       }
     }
   }
