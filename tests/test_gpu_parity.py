@@ -645,6 +645,18 @@ def test_batch_config_queries_sampled(ctx):
     small = [i for i in range(4096) if int(b[i] - a[i]) <= 2048][:8]
     for i in small:
         assert got[i] == oracle.search_range(int(a[i]), int(b[i]))
+    # Past the small-query class: queries of 2^13 .. 2^16 integers against the oracle.
+    mid = [i for i in range(4096) if 8192 < int(b[i] - a[i]) <= 1 << 16][:6]
+    assert len(mid) == 6
+    for i in mid:
+        say(f"  query {i}: [{int(a[i])}, {int(b[i])})")
+        assert got[i] == oracle.search_range(int(a[i]), int(b[i]))
+    # Every reported pair of every query is a pair of that query, by trial division.
+    for i, pairs in enumerate(got):
+        for m, n, kind in pairs:
+            assert int(a[i]) <= m < n < int(b[i])
+            rm, rm1, rn, rn1 = (oracle.rad(v) for v in (m, m + 1, n, n + 1))
+            assert (kind == 1 and rm == rn and rm1 == rn1) or (kind == 2 and rm == rn1 and rm1 == rn)
 
 
 # --- small-query class ------------------------------------------------------------------
