@@ -76,7 +76,7 @@ def device_squarefree_count(ctx, N, chunk=1 << 28):
     (1, 2), (1, 3), (5, 5), (1, 4097), (1, 4098), (1, (1 << 16) + 3), (1, (1 << 17) + 1),
     ((1 << 17) - 7, (1 << 17) + 9), ((1 << 20) - 100, (1 << 20) + 300),
     ((1 << 32) - 3000, (1 << 32) + 1000),
-    ((1 << 36) - 70000, (1 << 36) + 70000),  # crosses a segment boundary (segments of 2^17)
+    ((1 << 36) - 300000, (1 << 36) + 300000),  # two segments of 2^18 and many tiles
     ((1 << 40) - 5000, (1 << 40) + 5000),
     ((1 << 42) - 20001, (1 << 42) - 1),
 ])
