@@ -195,28 +195,35 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(uint64_t* out, uint64_t
 // [w * 1024, (w + 1) * 1024) of the tile, 64 consecutive items per step, so
 // index order is (wave, step, lane) order.  Lanes holding the same digit find
 // each other with eight ballots; the group's first lane advances the wave's
-// running count of that digit.  The digit's position is then the scanned
-// offset of (digit, tile), plus the counts of the earlier waves, plus the rank.
+// running count of that digit.  The tile is then sorted by digit in LDS
+// (keys, then values, through one staging array) and written out with
+// consecutive threads on consecutive positions of each digit's run: the
+// digit's run starts at the scanned offset of (digit, tile).
 __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint64_t* keys_in, const uint64_t* vals_in, uint64_t n,
                                                         uint32_t shift, const uint64_t* offs, uint64_t n_tiles,
                                                         uint64_t* keys_out, uint64_t* vals_out) {
   constexpr int W = kRsBlock / 64;
-  __shared__ uint32_t wc[W][256];
-  __shared__ uint64_t dofs[W][256];
+  static_assert(kRsBlock == 256, "one thread per digit below");
+  __shared__ uint32_t wc[W][256];   // running counts, then each (wave, digit)'s first tile position
+  __shared__ uint32_t tstart[256];  // first tile position of each digit
+  __shared__ uint64_t gofs[256];    // first output position of each digit's run
+  __shared__ uint32_t wsum[W];
+  __shared__ uint64_t stage[kRsTile];
+  __shared__ uint8_t sdig[kRsTile];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
 #pragma unroll
   for (int k = 0; k < W; ++k) wc[k][tid] = 0;
   __syncthreads();
   const uint64_t below = (1ull << lane) - 1ull;
-  const uint64_t base = blockIdx.x * static_cast<uint64_t>(kRsTile) + static_cast<uint64_t>(w) * (kRsTile / W);
-  uint64_t key[kRsIter], val[kRsIter];
-  uint32_t rank[kRsIter];
+  const uint64_t tile0 = blockIdx.x * static_cast<uint64_t>(kRsTile);
+  const uint64_t base = tile0 + static_cast<uint64_t>(w) * (kRsTile / W);
+  uint64_t key[kRsIter];
+  uint32_t pos[kRsIter];  // rank among the wave's equal digits, then the tile position
 #pragma unroll
   for (int it = 0; it < kRsIter; ++it) {
     const uint64_t i = base + it * 64 + lane;
     const bool ok = i < n;
     key[it] = ok ? keys_in[i] : 0;
-    val[it] = ok ? vals_in[i] : 0;
     const uint32_t d = static_cast<uint32_t>(key[it] >> shift) & 255u;
     uint64_t same = __ballot(ok);
 #pragma unroll
@@ -226,27 +233,53 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint64_t* keys_in
     }
     const uint32_t c0 = wc[w][d];
     if (ok && (same & below) == 0) wc[w][d] = c0 + static_cast<uint32_t>(__popcll(same));
-    rank[it] = c0 + static_cast<uint32_t>(__popcll(same & below));
+    pos[it] = c0 + static_cast<uint32_t>(__popcll(same & below));
   }
   __syncthreads();
   {
-    const uint32_t d = tid;  // kRsBlock == 256 digits
-    uint64_t s = offs[static_cast<uint64_t>(d) * n_tiles + blockIdx.x];
+    const uint32_t d = tid;
+    uint32_t c[W], tot = 0;
 #pragma unroll
     for (int k = 0; k < W; ++k) {
-      dofs[k][d] = s;
-      s += wc[k][d];
+      c[k] = wc[k][d];
+      tot += c[k];
     }
+    uint32_t all = 0;
+    uint32_t run = block_exclusive_scan<kRsBlock>(tot, wsum, &all);
+    tstart[d] = run;
+    gofs[d] = offs[static_cast<uint64_t>(d) * n_tiles + blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      wc[k][d] = run;
+      run += c[k];
+    }
+  }
+  __syncthreads();
+  const uint32_t m = static_cast<uint32_t>(min(static_cast<uint64_t>(kRsTile), n - tile0));  // items of the tile
+#pragma unroll
+  for (int it = 0; it < kRsIter; ++it) {
+    if (base + it * 64 + lane < n) {
+      const uint32_t d = static_cast<uint32_t>(key[it] >> shift) & 255u;
+      pos[it] += wc[w][d];
+      stage[pos[it]] = key[it];
+      sdig[pos[it]] = static_cast<uint8_t>(d);
+    }
+  }
+  __syncthreads();
+  for (uint32_t j = tid; j < m; j += kRsBlock) {
+    const uint32_t d = sdig[j];
+    keys_out[gofs[d] + (j - tstart[d])] = stage[j];
   }
   __syncthreads();
 #pragma unroll
   for (int it = 0; it < kRsIter; ++it) {
     const uint64_t i = base + it * 64 + lane;
-    if (i < n) {
-      const uint64_t pos = dofs[w][static_cast<uint32_t>(key[it] >> shift) & 255u] + rank[it];
-      keys_out[pos] = key[it];
-      vals_out[pos] = val[it];
-    }
+    if (i < n) stage[pos[it]] = vals_in[i];
+  }
+  __syncthreads();
+  for (uint32_t j = tid; j < m; j += kRsBlock) {
+    const uint32_t d = sdig[j];
+    vals_out[gofs[d] + (j - tstart[d])] = stage[j];
   }
 }
 
