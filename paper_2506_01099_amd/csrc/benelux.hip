@@ -142,6 +142,11 @@ struct bx_ctx {
   hipEvent_t last_done = nullptr;    // recorded after the last call's work
   hipStream_t last_stream = nullptr;  // stream that work ran on
   void* na = nullptr;  // this device's no-allocation scratch (NaDevice)
+  // Pinned host staging of the query tables (uploads need no wait for the host
+  // vectors) and the event after their last upload (the next upload waits for it).
+  void* pin = nullptr;
+  size_t pin_bytes = 0;
+  hipEvent_t pin_ev = nullptr;
   // serving
   struct Server;
   std::unique_ptr<Server> server;
@@ -562,18 +567,43 @@ void make_segs(const bx_ctx* c, Segs* s, bool small_class) {
   s->n_expect = static_cast<uint64_t>(std::ceil(expect));
 }
 
+// Uploads the query table, the segment prefix and the small-query list through
+// the context's pinned staging buffer: the copies are queued on st and the
+// call returns at once (the next upload waits for these copies first).  The
+// device tables are rewritten only once the kernels queued before on st,
+// which may read them, have finished: a small copy from pinned memory may be
+// carried out by the host at once rather than in stream order.
 int upload_segs(bx_ctx* c, const Segs& s, hipStream_t st) {
   int rc;
   if ((rc = ensure(c, c->queries, s.q.size() * sizeof(Query))) != BX_OK) return rc;
   if ((rc = ensure(c, c->segpref, s.prefix.size() * sizeof(uint64_t))) != BX_OK) return rc;
-  BX_HIP(hipMemcpyAsync(c->queries.p, s.q.data(), s.q.size() * sizeof(Query), hipMemcpyHostToDevice, st));
-  BX_HIP(hipMemcpyAsync(c->segpref.p, s.prefix.data(), s.prefix.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-  if (!s.small.empty()) {
-    if ((rc = ensure(c, c->smallq, s.small.size() * sizeof(uint32_t))) != BX_OK) return rc;
-    BX_HIP(hipMemcpyAsync(c->smallq.p, s.small.data(), s.small.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+  if (!s.small.empty() && (rc = ensure(c, c->smallq, s.small.size() * sizeof(uint32_t))) != BX_OK) return rc;
+  const size_t nq = s.q.size() * sizeof(Query), np = s.prefix.size() * sizeof(uint64_t),
+               ns = s.small.size() * sizeof(uint32_t);
+  const size_t op = (nq + 63) & ~size_t(63), os = op + ((np + 63) & ~size_t(63)), need = os + ns;
+  if (c->pin_ev) BX_HIP(hipEventSynchronize(c->pin_ev));  // the previous upload has left the buffer
+  BX_HIP(hipStreamSynchronize(st));  // earlier kernels are done with the tables
+  if (need > c->pin_bytes) {
+    if (c->pin) BX_HIP(hipHostFree(c->pin));
+    c->pin = nullptr;
+    c->pin_bytes = 0;
+    const size_t bytes = std::max<size_t>(need, 1 << 16);
+    if (hipHostMalloc(&c->pin, bytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      c->pin = nullptr;
+      return fail(BX_ENOMEM, "pinned host allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    c->pin_bytes = bytes;
   }
-  // The host vectors die with the caller: wait for the copies.
-  BX_HIP(hipStreamSynchronize(st));
+  if (!c->pin_ev) BX_HIP(hipEventCreateWithFlags(&c->pin_ev, hipEventDisableTiming));
+  uint8_t* h = static_cast<uint8_t*>(c->pin);
+  std::memcpy(h, s.q.data(), nq);
+  std::memcpy(h + op, s.prefix.data(), np);
+  if (ns) std::memcpy(h + os, s.small.data(), ns);
+  BX_HIP(hipMemcpyAsync(c->queries.p, h, nq, hipMemcpyHostToDevice, st));
+  BX_HIP(hipMemcpyAsync(c->segpref.p, h + op, np, hipMemcpyHostToDevice, st));
+  if (ns) BX_HIP(hipMemcpyAsync(c->smallq.p, h + os, ns, hipMemcpyHostToDevice, st));
+  if (!c->capturing) BX_HIP(hipEventRecord(c->pin_ev, st));
   return BX_OK;
 }
 
@@ -866,14 +896,17 @@ int enqueue_verify(bx_ctx* c, const Job& j, uint32_t grid, hipStream_t st) {
   return BX_OK;
 }
 
-int read_flags(bx_ctx* c, uint32_t* fl, hipStream_t st) {
+// The flag words and the 64-bit counters, read with one wait.
+int read_flags_acc(bx_ctx* c, uint32_t* fl, unsigned long long* acc, hipStream_t st) {
   BX_HIP(hipMemcpyAsync(fl, c->flags.p, kFlagCount * 4, hipMemcpyDeviceToHost, st));
+  BX_HIP(hipMemcpyAsync(acc, c->acc.p, kAccCount * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
   BX_HIP(hipStreamSynchronize(st));
   return BX_OK;
 }
 
-// Read the verified pairs (flags already read after the verify kernel).
-int collect_pairs(bx_ctx* c, const uint32_t* fl, hipStream_t st, std::vector<OutPair>* result) {
+// Read the verified pairs (flags and counters already read after the last kernel).
+int collect_pairs(bx_ctx* c, const uint32_t* fl, const unsigned long long* acc, hipStream_t st,
+                  std::vector<OutPair>* result) {
   if (fl[kFlagSpillOverflow]) return fail(BX_EINTERNAL, "sparse-hit spill buffer overflow");
   if (fl[kFlagCand] > kCandCap) return fail(BX_EINTERNAL, "candidate buffer overflow");
   if (fl[kFlagVerifyFail])
@@ -887,9 +920,6 @@ int collect_pairs(bx_ctx* c, const uint32_t* fl, hipStream_t st, std::vector<Out
     BX_HIP(hipMemcpyAsync(result->data(), c->out.p, n_out * sizeof(OutPair), hipMemcpyDeviceToHost, st));
     BX_HIP(hipStreamSynchronize(st));
   }
-  unsigned long long acc[kAccCount] = {0, 0};
-  BX_HIP(hipMemcpyAsync(acc, c->acc.p, sizeof(acc), hipMemcpyDeviceToHost, st));
-  BX_HIP(hipStreamSynchronize(st));
   c->stats.entries = acc[kAccEntries];
   c->stats.joined = acc[kAccJoined];
   std::sort(result->begin(), result->end(), [](const OutPair& x, const OutPair& y) {
@@ -911,19 +941,18 @@ int run_passes_checked(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* 
   for (uint64_t v = 0; v < j.plan.passes; ++v)
     pending.emplace_back((v << 32) / j.plan.passes, ((v + 1) << 32) / j.plan.passes);
   uint32_t cand_before = 0;
-  unsigned long long acc_before[kAccCount] = {0, 0};
-  uint32_t fl[kFlagCount];
+  unsigned long long acc_before[kAccCount] = {0, 0}, acc[kAccCount] = {0, 0};
+  uint32_t fl[kFlagCount] = {};
   if (!j.s->small.empty()) {  // a split pass rolls back to what the small class left
-    if ((rc = read_flags(c, fl, st)) != BX_OK) return rc;
+    if ((rc = read_flags_acc(c, fl, acc, st)) != BX_OK) return rc;
     cand_before = fl[kFlagCand];
-    BX_HIP(hipMemcpyAsync(acc_before, c->acc.p, sizeof(acc_before), hipMemcpyDeviceToHost, st));
-    BX_HIP(hipStreamSynchronize(st));
+    std::memcpy(acc_before, acc, sizeof(acc));
   }
   while (!pending.empty()) {
     const uint64_t ph_lo = pending.front().first, ph_hi = pending.front().second;
     pending.pop_front();
     if ((rc = enqueue_pass(c, j, ph_lo, ph_hi, st)) != BX_OK) return rc;
-    if ((rc = read_flags(c, fl, st)) != BX_OK) return rc;
+    if ((rc = read_flags_acc(c, fl, acc, st)) != BX_OK) return rc;
     c->stats.passes++;
     if (fl[kFlagSpillOverflow]) return fail(BX_EINTERNAL, "sparse-hit spill buffer overflow");
     if (fl[kFlagL1Overflow] || fl[kFlagL2Overflow]) {
@@ -941,15 +970,14 @@ int run_passes_checked(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* 
       continue;
     }
     cand_before = fl[kFlagCand];
-    BX_HIP(hipMemcpyAsync(acc_before, c->acc.p, sizeof(acc_before), hipMemcpyDeviceToHost, st));
-    BX_HIP(hipStreamSynchronize(st));
+    std::memcpy(acc_before, acc, sizeof(acc));
   }
-  if (cand_before > 0) {
+  if (cand_before > 0) {  // otherwise the last read is current
     if (cand_before > kCandCap) return fail(BX_EINTERNAL, "candidate buffer overflow");
     if ((rc = enqueue_verify(c, j, std::min<uint32_t>(cand_before, kVerifyGrid), st)) != BX_OK) return rc;
+    if ((rc = read_flags_acc(c, fl, acc, st)) != BX_OK) return rc;
   }
-  if ((rc = read_flags(c, fl, st)) != BX_OK) return rc;
-  return collect_pairs(c, fl, st, result);
+  return collect_pairs(c, fl, acc, st, result);
 }
 
 // All passes and the verification captured into one HIP graph and launched
@@ -1005,7 +1033,8 @@ int run_passes_graph(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* re
   BX_HIP(hipGraphLaunch(c->graph_exec, st));
   if (b) BX_HIP(hipEventRecord(b, st));
   uint32_t fl[kFlagCount];
-  if ((rc = read_flags(c, fl, st)) != BX_OK) return rc;
+  unsigned long long acc[kAccCount] = {0, 0};
+  if ((rc = read_flags_acc(c, fl, acc, st)) != BX_OK) return rc;
   if (a && b) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, a, b) == hipSuccess) c->stats.graph_ms += ms;
@@ -1017,7 +1046,7 @@ int run_passes_graph(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* re
     *redo = 1;
     return BX_OK;
   }
-  return collect_pairs(c, fl, st, result);
+  return collect_pairs(c, fl, acc, st, result);
 }
 
 // The hash-partitioned exact join over all queries of `s`.
@@ -1136,7 +1165,8 @@ int run_alg3(bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds, std::vector<OutP
   }
   c->stats.integers = b - a;
   uint32_t fl[kFlagCount];
-  if ((rc = read_flags(c, fl, st)) != BX_OK) return rc;
+  unsigned long long acc_f[kAccCount] = {0, 0};
+  if ((rc = read_flags_acc(c, fl, acc_f, st)) != BX_OK) return rc;
   if (fl[kFlagSpillOverflow]) return fail(BX_EINTERNAL, "sparse-hit overflow in the radical sieve");
   if (fl[kFlagCand] > kCandCap) return fail(BX_EINTERNAL, "candidate buffer overflow");
   if (fl[kFlagCand] > 0) {
@@ -1144,9 +1174,9 @@ int run_alg3(bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds, std::vector<OutP
     j.batch = 0;
     j.kinds = kinds;
     if ((rc = enqueue_verify(c, j, std::min<uint32_t>(fl[kFlagCand], kVerifyGrid), st)) != BX_OK) return rc;
-    if ((rc = read_flags(c, fl, st)) != BX_OK) return rc;
+    if ((rc = read_flags_acc(c, fl, acc_f, st)) != BX_OK) return rc;
   }
-  return collect_pairs(c, fl, st, result);
+  return collect_pairs(c, fl, acc_f, st, result);
 }
 
 // Algorithm 2 over [a, b): radicals in chunks, one list entry (fingerprint of
@@ -1250,7 +1280,8 @@ int run_alg2(bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds, std::vector<OutP
   }
   BX_HIP(hipGetLastError());
   uint32_t fl[kFlagCount];
-  if ((rc = read_flags(c, fl, st)) != BX_OK) return rc;
+  unsigned long long acc_f[kAccCount] = {0, 0};
+  if ((rc = read_flags_acc(c, fl, acc_f, st)) != BX_OK) return rc;
   if (fl[kFlagSpillOverflow]) return fail(BX_EINTERNAL, "sparse-hit overflow in the radical sieve");
   if (fl[kFlagL1Overflow]) return fail(BX_EINTERNAL, "Algorithm 2: list overflow");
   if (fl[kFlagCand] > kCandCap) return fail(BX_EINTERNAL, "candidate buffer overflow");
@@ -1259,9 +1290,9 @@ int run_alg2(bx_ctx* c, uint64_t a, uint64_t b, uint32_t kinds, std::vector<OutP
     j.batch = 0;
     j.kinds = kinds;
     if ((rc = enqueue_verify(c, j, std::min<uint32_t>(fl[kFlagCand], kVerifyGrid), st)) != BX_OK) return rc;
-    if ((rc = read_flags(c, fl, st)) != BX_OK) return rc;
+    if ((rc = read_flags_acc(c, fl, acc_f, st)) != BX_OK) return rc;
   }
-  rc = collect_pairs(c, fl, st, result);
+  rc = collect_pairs(c, fl, acc_f, st, result);
   c->stats.joined = n;
   return rc;
 }
@@ -1567,6 +1598,8 @@ void bx_destroy(bx_ctx* c) {
   reset_stats(c);
   for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
   if (c->last_done) (void)hipEventDestroy(c->last_done);
+  if (c->pin_ev) (void)hipEventDestroy(c->pin_ev);
+  if (c->pin) (void)hipHostFree(c->pin);
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   delete c;
 }
