@@ -592,19 +592,24 @@ def run_served(bx, seconds, fifo=True, budget_bytes=200 << 30, max_inflight=2):
 
 def run_fifo(bx, t, a, b):
     """The same trace on the plain range path, FIFO, one request at a time: each
-    search starts at its arrival or when the previous one ends, whichever is later."""
+    search starts at its arrival or when the previous one ends, whichever is later.
+    Per-kernel event timing is off, as on the serving lanes."""
     import numpy as np
 
     lat = []
     n_pairs = 0
-    t_start = time.perf_counter()
-    for i in range(t.size):
-        wait = t_start + t[i] - time.perf_counter()
-        if wait > 0:
-            time.sleep(wait)
-        n_pairs += len(bx.search_range(int(a[i]), int(b[i])))
-        lat.append(time.perf_counter() - (t_start + t[i]))
-    wall = time.perf_counter() - t_start
+    bx.set_option("timing", 0)
+    try:
+        t_start = time.perf_counter()
+        for i in range(t.size):
+            wait = t_start + t[i] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            n_pairs += len(bx.search_range(int(a[i]), int(b[i])))
+            lat.append(time.perf_counter() - (t_start + t[i]))
+        wall = time.perf_counter() - t_start
+    finally:
+        bx.set_option("timing", 1)
     lat = np.array(lat)
     return {"requests": int(t.size), "wall_s": wall, "integers_per_s": int((b - a).sum()) / wall,
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
