@@ -209,6 +209,8 @@ typedef struct {
   double graph_ms;            /* device time of the captured graph (batched calls) */
   uint64_t joined;            /* entries the join kernels read (equals entries)   */
   uint64_t false_candidates;  /* candidates whose sets differ (dropped by verify) */
+  uint32_t l2_entry_bytes;    /* bytes per second-level entry: 8 (compact words) or 12 */
+  uint32_t reserved;
 } bx_stats;
 int bx_get_stats(bx_ctx* ctx, bx_stats* out);
 
@@ -246,6 +248,17 @@ int bx_get_stats(bx_ctx* ctx, bx_stats* out);
  *                  (0 = 1024)
  *   "submit_wait"  serving: 1 = bx_submit queues (default), 0 = bx_submit
  *                  refuses with BX_EBUSY what cannot be admitted at once
+ *   "compact"      1 = the second partition level stores 8-byte words (the
+ *                  entry's segment, offset and low fingerprint bits; the
+ *                  partition index stands for the top bits) where the plan
+ *                  allows it: power-of-two segment, full fingerprints, hash
+ *                  join, and few enough random matches for the verification;
+ *                  0 = 12-byte entries throughout (default: the words keep too
+ *                  few fingerprint bits at 2^36, so the verification's extra
+ *                  work outweighs the bytes saved)
+ *   "compact_fp_bits" for tests of the compact join: keep only this many low
+ *                  fingerprint bits in a compact word (12 .. 40; 0 = all the
+ *                  word holds), so that different sets meet
  *   "schedule"     single-range searches (bx_benelux_search, bx_search_range):
  *                  0 = hash-partitioned passes (default); 1 = Algorithm 3's
  *                  schedule (chunks of s values overlapping by one, each

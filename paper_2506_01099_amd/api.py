@@ -70,7 +70,7 @@ class Benelux:
             "launches": dict(zip(names, list(st.launches))), "kernel_ms": dict(zip(names, list(st.kernel_ms))),
             "total_ms": st.total_ms, "b1_bits": st.b1_bits, "b2_bits": st.b2_bits,
             "seg_len": st.seg_len, "tile": st.tile, "graph_ms": st.graph_ms,
-            "joined": st.joined, "false_candidates": st.false_candidates,
+            "joined": st.joined, "false_candidates": st.false_candidates, "l2_entry_bytes": st.l2_entry_bytes,
         }
 
     def autotune(self, a, b, reps=1, path=None):

@@ -129,6 +129,8 @@ struct bx_ctx {
   uint32_t small_max = kSmallMaxLen;  // longest query of the small class (0: class off)
   int small_block = 1024;             // threads of a small-class workgroup
   int submit_wait = 1;                // 0: bx_submit refuses what cannot be admitted at once
+  int compact = 0;                    // 1: second-level entries as 8-byte words where the plan allows
+  uint32_t compact_fp_bits = 0;       // tests: fingerprint bits a compact word keeps (0 = all it can)
   int graph_batch = 1;      // batched calls run as one captured HIP graph
   bool capturing = false;   // no event records while a stream capture is open
   hipGraphExec_t graph_exec = nullptr;
@@ -655,7 +657,18 @@ struct Job {
   uint32_t sieve_grid = 0, B1 = 1, B2 = 1, G = 1, cpr = 1;
   uint64_t ngsub = 1, n_regions = 1, part_grid = 8;
   uint32_t gmask = 0;
+  // Compact second level (8-byte words): positions as (segment, offset), the
+  // low fingerprint bits above them.
+  bool compact = false;
+  uint32_t pos_bits = 0, seg_log2 = 0;
+  uint64_t low_mask = 0;
+  uint64_t fp_known = (1ull << kFpBits) - 1;  // fingerprint bits the candidates carry exactly
 };
+
+// Random matches a compact plan lets through to the verification (pairs of
+// different sets whose kept fingerprint bits, bucket and partition agree), at
+// most this many per call.
+constexpr double kCompactFalseMax = 2e4;
 
 // Bytes of every workspace buffer a job needs.
 struct JobBufs {
@@ -688,7 +701,31 @@ int plan_job(bx_ctx* c, Segs& s, int batch, uint32_t kinds, Job* j, JobBufs* nb)
   if (j->part_grid > 0x7FFFFFFFull) return fail(BX_EINTERNAL, "partition grid too large");
   j->gmask = batch ? kGrpMask : 0u;
   nb->l1 = j->n_regions * plan.cap1 * sizeof(Entry);
-  nb->l2 = j->ngsub * plan.cap2 * sizeof(Entry);
+  // Compact words need a power-of-two segment, the full fingerprint (no test
+  // mask), the hash join, and enough kept bits that random matches stay few.
+  {
+    const uint32_t sl = c->seg_len;
+    uint32_t lg = 0;
+    while ((1u << lg) < sl) ++lg;
+    uint32_t sb = 1;
+    while ((1ull << sb) < std::max<uint64_t>(2, s.n_segs)) ++sb;
+    j->seg_log2 = lg;
+    j->pos_bits = sb + lg;
+    const uint32_t f2 = 64 - std::min<uint32_t>(64, j->pos_bits);
+    const uint32_t keep = c->compact_fp_bits ? std::min(f2, c->compact_fp_bits) : f2;
+    const double per_pass = static_cast<double>(s.n_expect) / plan.passes;
+    const double false_est =
+        plan.passes * per_pass * per_pass / 2.0 / std::ldexp(1.0, static_cast<int>(keep + plan.b1bits + plan.b2bits));
+    j->compact = c->compact && (1u << lg) == sl && c->fp_mask == (1ull << kFpBits) - 1 && !c->join_sort &&
+                 f2 >= 24 && (c->compact_fp_bits || false_est <= kCompactFalseMax);
+    if (j->compact) {
+      j->low_mask = (1ull << keep) - 1;
+      const uint32_t b2shift = plan.b2bits ? kFpBits - plan.b2bits : kFpBits;
+      const uint64_t part = b2shift < kFpBits ? (((1ull << plan.b2bits) - 1) << b2shift) : 0ull;
+      j->fp_known = (part | j->low_mask) & ((1ull << kFpBits) - 1);
+    }
+  }
+  nb->l2 = j->ngsub * plan.cap2 * (j->compact ? sizeof(uint64_t) : sizeof(Entry));
   nb->cnt1 = j->n_regions * 4ull;
   nb->cnt2 = j->ngsub * 4ull;
   nb->cand = kCandCap * sizeof(Cand);
@@ -735,6 +772,7 @@ int prepare_job(bx_ctx* c, Segs& s, int batch, uint32_t kinds, hipStream_t st, J
   const Plan& plan = j->plan;
   c->stats.b1_bits = plan.b1bits;
   c->stats.b2_bits = plan.b2bits;
+  c->stats.l2_entry_bytes = j->compact ? 8u : 12u;
   c->stats.seg_len = c->seg_len;
   c->stats.tile = static_cast<uint32_t>(c->tile);
   return BX_OK;
@@ -790,14 +828,22 @@ int enqueue_pass(bx_ctx* c, const Job& j, uint64_t ph_lo, uint64_t ph_hi, hipStr
     Q.b2mask = j.B2 - 1;
     Q.gmask = j.gmask;
     Q.flags = d_flags;
+    Q.l2c = static_cast<uint64_t*>(c->l2.p);
+    Q.batch = j.batch;
+    Q.queries = static_cast<const Query*>(c->queries.p);
+    Q.seg_prefix = static_cast<const uint64_t*>(c->segpref.p);
+    Q.seg_log2 = j.seg_log2;
+    Q.pos_bits = j.pos_bits;
+    Q.low_mask = j.low_mask;
     {
       LaunchTimer t(c, K_PART, st);
+      const dim3 pg(static_cast<uint32_t>(j.part_grid));
       if (c->fp_mask != (1ull << kFpBits) - 1)
-        hipLaunchKernelGGL((k_partition<kPartBlock, true>), dim3(static_cast<uint32_t>(j.part_grid)), dim3(kPartBlock), 0,
-                           st, Q);
+        hipLaunchKernelGGL((k_partition<kPartBlock, true, false>), pg, dim3(kPartBlock), 0, st, Q);
+      else if (j.compact)
+        hipLaunchKernelGGL((k_partition<kPartBlock, false, true>), pg, dim3(kPartBlock), 0, st, Q);
       else
-        hipLaunchKernelGGL((k_partition<kPartBlock, false>), dim3(static_cast<uint32_t>(j.part_grid)), dim3(kPartBlock),
-                           0, st, Q);
+        hipLaunchKernelGGL((k_partition<kPartBlock, false, false>), pg, dim3(kPartBlock), 0, st, Q);
     }
     BX_HIP(hipGetLastError());
     JoinParams J;
@@ -810,9 +856,20 @@ int enqueue_pass(bx_ctx* c, const Job& j, uint64_t ph_lo, uint64_t ph_hi, hipStr
     J.cand_cap = kCandCap;
     J.flags = d_flags;
     J.joined = static_cast<unsigned long long*>(c->acc.p) + kAccJoined;
+    J.l2c = static_cast<const uint64_t*>(c->l2.p);
+    J.pos_bits = j.pos_bits;
+    J.seg_log2 = j.seg_log2;
+    J.seg_prefix = static_cast<const uint64_t*>(c->segpref.p);
+    J.queries = static_cast<const Query*>(c->queries.p);
+    J.n_queries = static_cast<uint32_t>(j.s->q.size());
+    J.batch = j.batch;
+    J.b2shift = plan.b2bits ? kFpBits - plan.b2bits : kFpBits;
+    J.b2mask = j.B2 - 1;
     {
       LaunchTimer t(c, K_JOIN, st);
-      if (c->join_sort)
+      if (j.compact)
+        hipLaunchKernelGGL((k_join_c<kJoinBlock>), dim3(static_cast<uint32_t>(j.ngsub)), dim3(kJoinBlock), 0, st, J);
+      else if (c->join_sort)
         hipLaunchKernelGGL((k_join_sort<kJoinBlock>), dim3(static_cast<uint32_t>(j.ngsub)), dim3(kJoinBlock), 0, st, J);
       else
         hipLaunchKernelGGL((k_join<kJoinBlock>), dim3(static_cast<uint32_t>(j.ngsub)), dim3(kJoinBlock), 0, st, J);
@@ -885,6 +942,7 @@ int enqueue_verify(bx_ctx* c, const Job& j, uint32_t grid, hipStream_t st) {
   V.kinds = j.kinds;
   V.third_off = c->third_off;
   V.fp_mask = c->fp_mask;
+  V.fp_known = j.fp_known;
   V.out = static_cast<OutPair*>(c->out.p);
   V.out_cap = kCandCap;
   V.flags = static_cast<uint32_t*>(c->flags.p);
@@ -991,11 +1049,12 @@ int run_passes_graph(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* re
   // Every launch shape, every option baked into a kernel argument or choice,
   // and every buffer address the graph's kernels use.
   std::snprintf(key, sizeof(key),
-                "%u %llu %u %u %u %u %llu %u %d %u %u %d %u %d %d %llx %u %d %zu %p %p %p %p %p %p %p %p %p %p %p %p %p %p",
+                "%u %llu %u %u %u %u %llu %u %d %u %u %d %u %d %d %llx %u %d %zu %d %u %llx %p %p %p %p %p %p %p %p %p %p %p %p %p %p",
                 j.plan.passes, static_cast<unsigned long long>(j.plan.cap1), j.plan.cap2, j.plan.b1bits, j.plan.b2bits,
                 j.G, static_cast<unsigned long long>(j.s->n_segs), static_cast<uint32_t>(j.s->q.size()), j.batch,
                 j.kinds, c->third_off, c->tile, c->seg_len, c->prune, c->join_sort,
-                static_cast<unsigned long long>(c->fp_mask), c->small_max, c->small_block, j.s->small.size(), c->l1.p,
+                static_cast<unsigned long long>(c->fp_mask), c->small_max, c->small_block, j.s->small.size(),
+                static_cast<int>(j.compact), j.pos_bits, static_cast<unsigned long long>(j.low_mask), c->l1.p,
                 c->l2.p, c->spill.p, c->cnt1.p, c->cnt2.p, c->cand.p, c->out.p, c->flags.p, c->acc.p, c->queries.p,
                 c->segpref.p, c->smallq.p, static_cast<void*>(c->d_pp), static_cast<void*>(c->d_primes));
   if (!c->graph_exec || c->graph_key != key) {
@@ -1656,6 +1715,11 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
     c->force_group = static_cast<int>(v);
   } else if (n == "submit_wait") {
     c->submit_wait = v != 0;
+  } else if (n == "compact") {
+    c->compact = v != 0;
+  } else if (n == "compact_fp_bits") {
+    if (v != 0 && (v < 12 || v > 40)) return fail(BX_EINVAL, "compact_fp_bits must be 0 or in [12, 40]");
+    c->compact_fp_bits = static_cast<uint32_t>(v);
   } else if (n == "small_max") {
     if (v < 0 || v > static_cast<int64_t>(kSmallMaxLen)) return fail(BX_EINVAL, "small_max must be in [0, 8192]");
     c->small_max = static_cast<uint32_t>(v);
@@ -1898,6 +1962,8 @@ int bx_serve_start(bx_ctx* c, uint64_t budget_bytes, int max_inflight) {
     lane->force_group = c->force_group;
     lane->small_max = c->small_max;
     lane->small_block = c->small_block;
+    lane->compact = c->compact;
+    lane->compact_fp_bits = c->compact_fp_bits;
     lane->timing = 0;
     lane->graph_batch = 0;  // batch shapes change from batch to batch: no graph reuse
     S->lanes.push_back(lane);

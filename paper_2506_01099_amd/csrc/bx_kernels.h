@@ -18,6 +18,8 @@
 //   k_fill_u32          fills a word array (clears counters inside graphs).
 //   k_set_query         writes a one-query table from kernel arguments.
 #pragma once
+#include <type_traits>
+
 #include "bx_device.h"
 
 namespace bx {
@@ -114,8 +116,8 @@ struct SieveShSel<T, BLOCK, MODE_KEYS> {
 // bucket b: shared by all workgroups (global, one atomic per non-empty bucket)
 // or, with PRIVATE, owned by this workgroup (no atomics).  dst(b, k) stores the
 // k-th entry of the bucket (k < cap).
-template <int BLOCK, int NB, int NMAX, bool PRIVATE, typename Bucket, typename Dst, typename Mid>
-__device__ void scatter_runs(uint32_t n, uint32_t nb, const Entry* ent, Bucket sb, uint16_t* perm,
+template <int BLOCK, int NB, int NMAX, bool PRIVATE, typename Item, typename Bucket, typename Dst, typename Mid>
+__device__ void scatter_runs(uint32_t n, uint32_t nb, const Item* ent, Bucket sb, uint16_t* perm,
                              uint32_t* cnt, uint32_t* gofs, uint32_t* wsum, uint32_t* gcur, uint64_t cap,
                              uint32_t* flag, Dst dst, Mid mid) {
   constexpr int BINS = (NB + BLOCK - 1) / BLOCK;
@@ -179,7 +181,7 @@ __device__ void scatter_runs(uint32_t n, uint32_t nb, const Entry* ent, Bucket s
     pi[u] = perm[j < n ? j : 0u];
   }
   uint32_t pb[U];
-  Entry pe[U];
+  Item pe[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     pb[u] = sb(pi[u]);
@@ -602,7 +604,30 @@ struct PartParams {
   uint64_t fp_mask;          // fingerprint bits kept (all 53 but in tests of the verification)
   uint32_t gmask;
   uint32_t* flags;
+  // Compact second level: one 64-bit word per entry, fp_low << pos_bits |
+  // s << seg_log2 | off, with s the global segment of x and off its offset in
+  // that segment (the top of the fingerprint is the partition's own index).
+  uint64_t* l2c;
+  int batch;
+  const Query* queries;
+  const uint64_t* seg_prefix;
+  uint32_t seg_log2, pos_bits;
+  uint64_t low_mask;  // fingerprint bits a compact word keeps
 };
+
+__device__ __forceinline__ uint64_t compact_word(const PartParams& P, const Entry& e) {
+  const uint64_t pos = entry_pos43(e);
+  uint64_t rel, s0;
+  if (P.batch) {
+    rel = pos & ((1ull << kGrpShift) - 1);
+    s0 = P.seg_prefix[(pos >> kGrpShift) & kGrpMask];
+  } else {
+    rel = pos - P.queries[0].a;
+    s0 = 0;
+  }
+  const uint64_t seg = s0 + (rel >> P.seg_log2), off = rel & ((1ull << P.seg_log2) - 1);
+  return ((entry_fp(e) & P.low_mask) << P.pos_bits) | (seg << P.seg_log2) | off;
+}
 
 // Second scatter of one group of first-level buckets into the group buffer.
 // Persistent: workgroup l runs on XCD l mod 8 (round-robin dispatch) and
@@ -611,11 +636,12 @@ struct PartParams {
 // before they are written back.  The bucket's chunks are split into nbw
 // contiguous ranges, one per workgroup; the next chunk is loaded into
 // registers while the current one is scattered.
-template <int BLOCK, bool MASK_FP>
+template <int BLOCK, bool MASK_FP, bool COMPACT>
 __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
   constexpr int EPT = kPartChunk / BLOCK;
   static_assert(kPartChunk % BLOCK == 0, "chunk shape");
-  __shared__ Entry ent[kPartChunk];
+  using Item = typename std::conditional<COMPACT, uint64_t, Entry>::type;  // what the chunk stages
+  __shared__ Item ent[kPartChunk];
   __shared__ uint16_t sbk[kPartChunk], perm[kPartChunk];
   __shared__ uint32_t cnt[kB2Max], gofs[kB2Max];
   __shared__ uint32_t wsum[BLOCK / 64];
@@ -632,6 +658,7 @@ __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
   const uint64_t n_chunks = static_cast<uint64_t>(P.W) * cpr;
   const uint64_t c_begin = n_chunks * k / nbw, c_end = n_chunks * (k + 1) / nbw;
   Entry* out = P.l2 + static_cast<uint64_t>(gb) * B2 * P.cap2;
+  uint64_t* outc = P.l2c + static_cast<uint64_t>(gb) * B2 * P.cap2;
   uint32_t* gcur = P.cnt2 + static_cast<uint64_t>(gb) * B2;
   const uint32_t cap2 = P.cap2;
   // The partition of an entry is the top of its fingerprint.
@@ -662,7 +689,10 @@ __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
           const uint64_t pos43 = entry_pos43(x);
           x = make_entry(pos43, entry_fp(x) & P.fp_mask);
         }
-        ent[i] = x;
+        if constexpr (COMPACT)
+          ent[i] = compact_word(P, x);
+        else
+          ent[i] = x;
         sbk[i] = static_cast<uint16_t>(static_cast<uint32_t>(entry_fp(e[q]) >> P.b2shift) & P.b2mask);
       }
     }
@@ -681,7 +711,13 @@ __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
     if (n_cur)  // uniform over the workgroup
       scatter_runs<BLOCK, kB2Max, kPartChunk, false>(
           n_cur, B2, ent, bucket_of, perm, cnt, gofs, wsum, gcur, cap2, &P.flags[kFlagL2Overflow],
-          [=](uint32_t b, uint32_t kk, const Entry& x) { out[static_cast<uint64_t>(b) * cap2 + kk] = x; }, prefetch);
+          [=](uint32_t b, uint32_t kk, const Item& x) {
+            if constexpr (COMPACT)
+              outc[static_cast<uint64_t>(b) * cap2 + kk] = x;
+            else
+              out[static_cast<uint64_t>(b) * cap2 + kk] = x;
+          },
+          prefetch);
     else
       prefetch();
   }
@@ -697,7 +733,34 @@ struct JoinParams {
   uint32_t cand_cap;
   uint32_t* flags;
   unsigned long long* joined;  // entries read, summed over partitions (64-bit: 2^36 searches pass 2^32)
+  // Compact second level (k_join_c): the words and what decodes them.
+  const uint64_t* l2c;
+  uint32_t pos_bits, seg_log2;
+  const uint64_t* seg_prefix;
+  const Query* queries;
+  uint32_t n_queries;
+  int batch;
+  uint32_t b2shift, b2mask;  // the partition index is the top of the fingerprint
 };
+
+// The 12-byte entry of a compact word: x from its segment and offset, and the
+// fingerprint bits known (the partition's index on top, the kept low bits).
+__device__ __forceinline__ Entry compact_entry(const JoinParams& P, uint64_t w, uint64_t sbk) {
+  const uint64_t off = w & ((1ull << P.seg_log2) - 1);
+  const uint64_t seg = (w & ((1ull << P.pos_bits) - 1)) >> P.seg_log2;
+  uint32_t lo = 0, hi = P.n_queries;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (P.seg_prefix[mid] <= seg)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const uint64_t rel = ((seg - P.seg_prefix[lo]) << P.seg_log2) | off;
+  const uint64_t pos43 = P.batch ? (rel | (static_cast<uint64_t>(lo) << kGrpShift)) : P.queries[0].a + rel;
+  const uint64_t part = P.b2shift < kFpBits ? ((sbk & P.b2mask) << P.b2shift) : 0ull;
+  return make_entry(pos43, part | (w >> P.pos_bits));
+}
 
 __device__ __forceinline__ void emit_cand(const JoinParams& P, const Entry& a, const Entry& b) {
   const uint32_t k = atomicAdd(&P.flags[kFlagCand], 1u);
@@ -813,6 +876,102 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
   }
 }
 
+// k_join over compact words: the same inserts and probes, on the kept low
+// fingerprint bits (the partition fixes the top ones); a match is decoded into
+// 12-byte entries for the verification, which also drops matches of different
+// queries.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void k_join_c(JoinParams P) {
+  constexpr int EPT = kJoinCap / BLOCK;
+  constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+  constexpr uint32_t kIdxMask = (1u << kJoinIdxBits) - 1;
+  static_assert(kJoinCap < (1 << kJoinIdxBits), "index field must not reach the empty marker");
+  __shared__ __align__(16) uint32_t table[kJoinSlots];
+  const int tid = threadIdx.x;
+  const uint64_t sbk = blockIdx.x;
+  if (sbk >= P.n_sub) return;
+  const uint32_t n = min(P.cnt2[sbk], P.cap2);
+  __syncthreads();
+  if (tid == 0) {
+    P.cnt2[sbk] = 0;
+    if (n) atomicAdd(P.joined, static_cast<unsigned long long>(n));
+  }
+  if (n < 2) return;
+  const uint64_t* src = P.l2c + sbk * P.cap2;
+  const uint32_t pb = P.pos_bits;
+  auto emit = [&](uint64_t a, uint64_t b) {
+    const uint32_t k = atomicAdd(&P.flags[kFlagCand], 1u);
+    if (k < P.cand_cap) {
+      Cand c;
+      c.a = compact_entry(P, a, sbk);
+      c.b = compact_entry(P, b, sbk);
+      P.cand[k] = c;
+    }
+  };
+  for (uint32_t i0 = 0; i0 < n; i0 += kJoinCap) {
+    const uint32_t m = min(static_cast<uint32_t>(kJoinCap), n - i0);
+    uint32_t slots = 1024;
+    while (slots < 2 * m && slots < static_cast<uint32_t>(kJoinSlots)) slots <<= 1;
+    const uint32_t smask = slots - 1;
+    uint64_t e[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const uint32_t i = tid + k * BLOCK;
+      e[k] = src[i0 + (i < m ? i : 0u)];
+    }
+    for (uint32_t s = 4 * tid; s < slots; s += 4 * BLOCK)
+      *reinterpret_cast<uint4*>(&table[s]) = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+    __syncthreads();
+    constexpr int kClaim = EPT < 4 ? EPT : 4;
+    static_assert(EPT % kClaim == 0, "claim groups");
+#pragma unroll
+    for (int k0 = 0; k0 < EPT; k0 += kClaim) {
+      uint32_t got[kClaim];
+#pragma unroll
+      for (int u = 0; u < kClaim; ++u) {
+        const uint32_t i = tid + (k0 + u) * BLOCK;
+        const uint32_t h = static_cast<uint32_t>(e[k0 + u] >> pb);
+        got[u] = i < m ? atomicCAS(&table[h & smask], kEmpty, (h & ~kIdxMask) | i) : kEmpty;
+      }
+#pragma unroll
+      for (int u = 0; u < kClaim; ++u) {
+        if (got[u] == kEmpty) continue;
+        const int k = k0 + u;
+        const uint64_t fk = e[k] >> pb;
+        const uint32_t h = static_cast<uint32_t>(fk);
+        const uint32_t mine = (h & ~kIdxMask) | (tid + k * BLOCK);
+        uint32_t v = got[u], s = h & smask;
+        for (;;) {
+          if (((v ^ mine) & ~kIdxMask) == 0) {
+            const uint64_t f = src[i0 + (v & kIdxMask)];
+            if ((f >> pb) == fk) emit(e[k], f);
+          }
+          s = (s + 1) & smask;
+          v = atomicCAS(&table[s], kEmpty, mine);
+          if (v == kEmpty) break;
+        }
+      }
+    }
+    __syncthreads();
+    for (uint32_t jj = i0 + m + tid; jj < n; jj += BLOCK) {
+      const uint64_t g = src[jj];
+      const uint64_t fk = g >> pb;
+      const uint32_t h = static_cast<uint32_t>(fk);
+      uint32_t s = h & smask;
+      for (;;) {
+        const uint32_t v = table[s];
+        if (v == kEmpty) break;
+        if (((v ^ h) & ~kIdxMask) == 0) {
+          const uint64_t f = src[i0 + (v & kIdxMask)];
+          if ((f >> pb) == fk) emit(g, f);
+        }
+        s = (s + 1) & smask;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Sort join of one second-level partition, the ablation of the LDS hash join:
 // Algorithm 2 (sort, then compare neighbours) applied per partition, with every
 // pair of a run of equal keys reported rather than adjacent ones only.  The low
@@ -907,6 +1066,7 @@ struct VerifyParams {
   uint32_t kinds;
   uint32_t third_off;  // the third condition compares rad(m + third_off), rad(n + third_off) (2 in use)
   uint64_t fp_mask;
+  uint64_t fp_known;  // fingerprint bits the candidates carry exactly (all but after a compact join)
   OutPair* out;
   uint32_t out_cap;
   uint32_t* flags;
@@ -975,10 +1135,11 @@ __global__ __launch_bounds__(BLOCK) void k_verify(VerifyParams P) {
       }
       const uint64_t lo_m = rad[0] < rad[1] ? rad[0] : rad[1], hi_m = rad[0] < rad[1] ? rad[1] : rad[0];
       const uint64_t lo_n = rad[2] < rad[3] ? rad[2] : rad[3], hi_n = rad[2] < rad[3] ? rad[3] : rad[2];
-      const bool same = (lo_m == lo_n) && (hi_m == hi_n) && m != n;
+      const bool same = (lo_m == lo_n) && (hi_m == hi_n) && m != n &&
+                        entry_grp(cd.b, P.batch ? kGrpMask : 0u) == qa_idx;
       if (!same) {
-        atomicAdd(&P.flags[kFlagFalseCand], 1u);  // equal fingerprints, different sets
-      } else if (((key64(lo_m, hi_m, P.batch ? qa_idx : 0u) >> 11) & P.fp_mask) != entry_fp(cd.a)) {
+        atomicAdd(&P.flags[kFlagFalseCand], 1u);  // equal fingerprints, different sets (or queries)
+      } else if ((((key64(lo_m, hi_m, P.batch ? qa_idx : 0u) >> 11) & P.fp_mask) ^ entry_fp(cd.a)) & P.fp_known) {
         atomicAdd(&P.flags[kFlagVerifyFail], 1u);  // the entry does not hold this set's fingerprint
       } else {
         // Kind 1 iff rad(m) = rad(n) (Algorithm 2); the third-condition bit

@@ -99,6 +99,28 @@ def group_keys(rad, a, b, grp, b1_bits, passes, fp_bits, prune=True):
     return (((pidx << np.uint64(10) | bucket) << np.uint64(15) | g) << np.uint64(32)) | fpc, int(keep.sum())
 
 
+def compact_keys(rad, a, b, grp, b1_bits, b2_bits, keep_bits):
+    """For the query [a, b), the group of every kept entry under the compact second
+    level (one pass): entries meet when their first-level bucket (low b1_bits of the
+    key hash), their partition (top b2_bits of the 53-bit fingerprint) and the low
+    keep_bits of the fingerprint agree -- the query itself is not compared (the
+    verification drops matches across queries)."""
+    n = b - a
+    x = np.arange(a, b, dtype=np.int64)
+    r = rad.astype(np.int64)
+    r0, r1 = r[:n], r[1:n + 1]
+    keep = kept(x, r0, r1, b)
+    u0, u1 = r0[keep].astype(np.uint64), r1[keep].astype(np.uint64)
+    lo, hi = np.minimum(u0, u1), np.maximum(u0, u1)
+    h = key64(lo, hi, np.full(lo.shape, grp, dtype=np.uint64))
+    bucket = h & np.uint64((1 << b1_bits) - 1)
+    fp = h >> np.uint64(11)
+    part = fp >> np.uint64(53 - b2_bits) if b2_bits else np.zeros_like(fp)
+    low = fp & np.uint64((1 << keep_bits) - 1)
+    assert b1_bits + b2_bits + keep_bits <= 64
+    return (((bucket << np.uint64(b2_bits)) | part) << np.uint64(keep_bits)) | low, int(keep.sum())
+
+
 def candidates(keys):
     """Pairs inside groups of equal keys: sum of k(k-1)/2."""
     if keys.size == 0:

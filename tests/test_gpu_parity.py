@@ -496,6 +496,95 @@ def test_join_candidates_exact_batched(ctx):
     assert st["candidates"] == want
 
 
+def test_compact_words_match_oracle(ctx):
+    """The second partition level as 8-byte words (segment, offset, low fingerprint
+    bits) and as 12-byte entries give the oracle's lists."""
+    from paper_2506_01099_amd.inputs import planted_queries
+
+    a, b = planted_queries()
+    for compact, nbytes in ((1, 8), (0, 12)):
+        ctx.set_option("compact", compact)
+        try:
+            for N in (1 << 20, (1 << 24) + 77):
+                assert ctx.search(N) == oracle.search(N), (compact, N)
+                assert ctx.stats()["l2_entry_bytes"] == nbytes
+            got = ctx.search_batch(a, b)
+            assert ctx.stats()["l2_entry_bytes"] == nbytes
+        finally:
+            ctx.set_option("compact", 0)
+        for i in range(a.size):
+            assert got[i] == oracle.search_range(int(a[i]), int(b[i]))
+
+
+@pytest.mark.parametrize("keep", [14, 16])
+def test_compact_candidates_exact_2_24(ctx, keep):
+    """Join completeness on compact words, counted exactly: with only `keep` low
+    fingerprint bits in a word, different sets meet, and every pair of equal (bucket,
+    partition, kept bits) must become a candidate."""
+    N = 1 << 24
+    ctx.set_option("compact", 1)
+    ctx.set_option("compact_fp_bits", keep)
+    try:
+        got = ctx.search(N)
+        st = ctx.stats()
+    finally:
+        ctx.set_option("compact_fp_bits", 0)
+        ctx.set_option("compact", 0)
+    assert got == oracle.search(N)
+    assert st["l2_entry_bytes"] == 8 and st["retries"] == 0
+    keys, n_kept = join_model.compact_keys(oracle.radicals(1, N + 2), 1, N + 1, 0, st["b1_bits"], st["b2_bits"], keep)
+    want = join_model.candidates(keys)
+    assert st["entries"] == st["joined"] == n_kept
+    assert 10**3 < want < 10**6
+    assert st["candidates"] == want
+    assert st["candidates"] == st["pairs"] + st["false_candidates"]
+
+
+def test_compact_candidates_exact_2_28(ctx, rad_2_28):
+    """The same at 2^28 (several first-level buckets), from the library's radicals."""
+    N, keep = 1 << 28, 18
+    ctx.set_option("compact", 1)
+    ctx.set_option("compact_fp_bits", keep)
+    try:
+        got = ctx.search(N)
+        st = ctx.stats()
+    finally:
+        ctx.set_option("compact_fp_bits", 0)
+        ctx.set_option("compact", 0)
+    assert got == theorem1_pairs(N)
+    assert st["l2_entry_bytes"] == 8 and st["b1_bits"] >= 1
+    keys, n_kept = join_model.compact_keys(rad_2_28, 1, N + 1, 0, st["b1_bits"], st["b2_bits"], keep)
+    want = join_model.candidates(keys)
+    assert st["entries"] == st["joined"] == n_kept
+    assert 10**3 < want < 10**6
+    assert st["candidates"] == want
+
+
+def test_compact_candidates_exact_batched(ctx):
+    """Batched compact words: matches across queries are candidates too (the words do
+    not hold the query) and the verification drops them."""
+    qs = [(1, 1 << 22), (1 << 22, 3 << 21), (5 << 30, (5 << 30) + (1 << 22))]
+    keep = 14
+    ctx.set_option("compact", 1)
+    ctx.set_option("compact_fp_bits", keep)
+    try:
+        got = ctx.search_batch(np.array([q[0] for q in qs], dtype=np.uint64),
+                               np.array([q[1] for q in qs], dtype=np.uint64))
+        st = ctx.stats()
+    finally:
+        ctx.set_option("compact_fp_bits", 0)
+        ctx.set_option("compact", 0)
+    allkeys = []
+    for i, (a, b) in enumerate(qs):
+        assert got[i] == oracle.search_range(a, b)
+        keys, _ = join_model.compact_keys(oracle.radicals(a, b + 1), a, b, i, st["b1_bits"], st["b2_bits"], keep)
+        allkeys.append(keys)
+    want = join_model.candidates(np.concatenate(allkeys))
+    assert st["l2_entry_bytes"] == 8 and st["retries"] == 0 and want > 10**3
+    assert st["candidates"] == want
+    assert st["candidates"] == st["pairs"] + st["false_candidates"]
+
+
 @pytest.mark.parametrize("passes", [1, 2, 3, 5, 7, 16, 64])
 def test_pass_count_invariance(ctx, passes):
     ctx.set_option("passes", passes)
