@@ -172,7 +172,8 @@ def parse_counters(fetch_dir, write_dir):
     w_scale = CALIB_BYTES / (w_copy * 1024) if w_copy else None
     out = {"source_hash": kernel_source_hash(), "calib_bytes": CALIB_BYTES,
            "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
-    for k, key in (("sieve", "k_sieve<"), ("partition", "k_partition<"), ("join", "k_join<")):
+    for k, keys in (("sieve", ("k_sieve<",)), ("partition", ("k_partition<",)), ("join", ("k_join<", "k_join_c<"))):
+        key = next((kk for kk in keys if any(kk in name for name in fetch)), keys[0])
         f, w = pick(fetch, key), pick(write, key)
         if f is None or w is None or not f_scale or not w_scale:
             continue
@@ -227,6 +228,7 @@ def run_plain(bx, N, steps, warmup, warm_s=None):
 
 def roofline_from(agg, n_ints_per_step, entries_per_step, steps, traffic):
     ms = agg["kernel_ms"]
+    l2 = agg.get("l2_entry_bytes") or ENTRY_BYTES  # second-level entry: 12 B, or an 8 B compact word
     ln = agg["launches"]
     kinds = {k: ms[k] for k in ("sieve", "partition", "join")}
     dominant = max(kinds, key=kinds.get)
@@ -239,24 +241,25 @@ def roofline_from(agg, n_ints_per_step, entries_per_step, steps, traffic):
         out["sieve"] = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_INT_OPS / 1e12, "unit": "Tops/s",
                         "frac": ach / (VALU_PEAK_INT_OPS / 1e12), "traffic": traffic.get("sieve"),
                         "avg_launch_ms": avg_ms, "integers_per_launch": ints_per_launch}
-    # Partition: HBM-bound, 12 B read + 12 B write per entry (the entries the
-    # sieve wrote: the integers that pass the member test).
+    # Partition: HBM-bound, a 12 B read and a 12 B (or 8 B compact) write per
+    # entry (the entries the sieve wrote: the integers that pass the member test).
     if ln["partition"]:
         avg_ms = ms["partition"] / ln["partition"]
-        b = 2 * ENTRY_BYTES * entries_per_step * steps / ln["partition"]
+        b = (ENTRY_BYTES + l2) * entries_per_step * steps / ln["partition"]
         ach = b / (avg_ms * 1e-3) / 1e9
         out["partition"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": ach / HBM_PEAK_GBS, "traffic": traffic.get("partition"), "avg_launch_ms": avg_ms,
                             "bytes_per_launch": b}
     if ln["join"]:
         avg_ms = ms["join"] / ln["join"]
-        b = ENTRY_BYTES * entries_per_step * steps / ln["join"]
+        b = l2 * entries_per_step * steps / ln["join"]
         ach = b / (avg_ms * 1e-3) / 1e9
         out["join"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": ach / HBM_PEAK_GBS, "traffic": traffic.get("join"), "avg_launch_ms": avg_ms,
                        "bytes_per_launch": b}
-    # The join as a whole (second scatter + LDS join): 32 B per key algorithmic
-    # (one 12 B entry written by the sieve, read once), over the join kernels' time.
+    # The join as a whole (second scatter + LDS join) against 24 B per key (the
+    # sieve's 12 B entry read and its second-level copy written), whatever the
+    # second-level format, over the join kernels' time.
     if ln["partition"] and ln["join"]:
         t = (ms["partition"] + ms["join"]) * 1e-3
         ach = 2 * ENTRY_BYTES * entries_per_step * steps / t / 1e9
@@ -337,6 +340,7 @@ def main():
         "data": "synthetic: the integers 1..N themselves (no dataset)",
         "config": {"workload": f"plain search N=2^{args.log2n}, both kinds, hash-partitioned passes",
                    "N": N, "member_test": True, "passes": agg["passes"], "b1_bits": agg["b1_bits"], "b2_bits": agg["b2_bits"],
+                   "second_level_entry_bytes": agg.get("l2_entry_bytes"),
                    "seg_len": agg["seg_len"], "tile": agg["tile"], "parallelism": "single GPU"},
         "pairs_found": len(pairs),
         "roofline": dict(roof[dominant], kernel=dominant),

@@ -248,14 +248,13 @@ int bx_get_stats(bx_ctx* ctx, bx_stats* out);
  *                  (0 = 1024)
  *   "submit_wait"  serving: 1 = bx_submit queues (default), 0 = bx_submit
  *                  refuses with BX_EBUSY what cannot be admitted at once
- *   "compact"      1 = the second partition level stores 8-byte words (the
+ *   "compact"      the second partition level stores 8-byte words (the
  *                  entry's segment, offset and low fingerprint bits; the
- *                  partition index stands for the top bits) where the plan
- *                  allows it: power-of-two segment, full fingerprints, hash
- *                  join, and few enough random matches for the verification;
- *                  0 = 12-byte entries throughout (default: the words keep too
- *                  few fingerprint bits at 2^36, so the verification's extra
- *                  work outweighs the bytes saved)
+ *                  partition index stands for the top bits) instead of 12-byte
+ *                  entries where the plan allows it: power-of-two segment,
+ *                  full fingerprints, hash join, and at most 3e5 expected
+ *                  random matches for the verification.  0 = never, 1 =
+ *                  single-range calls (default), 2 = batched calls too
  *   "compact_fp_bits" for tests of the compact join: keep only this many low
  *                  fingerprint bits in a compact word (12 .. 40; 0 = all the
  *                  word holds), so that different sets meet

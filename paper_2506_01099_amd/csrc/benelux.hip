@@ -112,6 +112,7 @@ struct bx_ctx {
   std::vector<double> cum_inv_q;  // cum_inv_q[i] = sum of 1/q over pp[0, i)
   uint32_t n_dense[2] = {0, 0};  // per tile shape (small, large)
   uint32_t* d_primes = nullptr;
+  PrimeInv* d_pinv = nullptr;  // per prime: p^-1 mod 2^64 and floor((2^64 - 1) / p) (divisibility tests)
   PrimePow* d_pp = nullptr;
   DenseTab* d_dense[2] = {nullptr, nullptr};
   DevBuf l1, l2, cnt1, cnt2, cand, out, flags, spill, queries, segpref, rad, acc, a3tab, smallq;
@@ -129,7 +130,7 @@ struct bx_ctx {
   uint32_t small_max = kSmallMaxLen;  // longest query of the small class (0: class off)
   int small_block = 1024;             // threads of a small-class workgroup
   int submit_wait = 1;                // 0: bx_submit refuses what cannot be admitted at once
-  int compact = 0;                    // 1: second-level entries as 8-byte words where the plan allows
+  int compact = 1;                    // 8-byte second-level words where the plan allows: 0 never, 1 single-range calls, 2 all
   uint32_t compact_fp_bits = 0;       // tests: fingerprint bits a compact word keeps (0 = all it can)
   int graph_batch = 1;      // batched calls run as one captured HIP graph
   bool capturing = false;   // no event records while a stream capture is open
@@ -308,6 +309,20 @@ int build_tables(bx_ctx* c) {
     BX_HIP(hipMemcpy(c->d_dense[which], &dt, sizeof(DenseTab), hipMemcpyHostToDevice));
   }
   BX_HIP(hipMalloc(&c->d_primes, std::max<size_t>(4, c->primes.size() * sizeof(uint32_t))));
+  {
+    // x is a multiple of odd p iff x * p^-1 mod 2^64 <= floor((2^64 - 1) / p)
+    // (Granlund & Montgomery 1994), and the product is then x / p.
+    std::vector<PrimeInv> inv(c->primes.size());
+    for (size_t i = 0; i < c->primes.size(); ++i) {
+      const uint64_t p = c->primes[i];
+      uint64_t x = p;  // p^-1 mod 2^3 for odd p; each Newton step doubles the correct bits
+      for (int k = 0; k < 5; ++k) x *= 2 - p * x;
+      inv[i] = PrimeInv{p & 1 ? x : 0, p & 1 ? UINT64_MAX / p : 0};
+    }
+    BX_HIP(hipMalloc(&c->d_pinv, std::max<size_t>(sizeof(PrimeInv), inv.size() * sizeof(PrimeInv))));
+    if (!inv.empty())
+      BX_HIP(hipMemcpy(c->d_pinv, inv.data(), inv.size() * sizeof(PrimeInv), hipMemcpyHostToDevice));
+  }
   BX_HIP(hipMalloc(&c->d_pp, std::max<size_t>(sizeof(PrimePow), c->pp.size() * sizeof(PrimePow))));
   if (!c->primes.empty())
     BX_HIP(hipMemcpy(c->d_primes, c->primes.data(), c->primes.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
@@ -668,7 +683,7 @@ struct Job {
 // Random matches a compact plan lets through to the verification (pairs of
 // different sets whose kept fingerprint bits, bucket and partition agree), at
 // most this many per call.
-constexpr double kCompactFalseMax = 2e4;
+constexpr double kCompactFalseMax = 3e5;
 
 // Bytes of every workspace buffer a job needs.
 struct JobBufs {
@@ -716,8 +731,11 @@ int plan_job(bx_ctx* c, Segs& s, int batch, uint32_t kinds, Job* j, JobBufs* nb)
     const double per_pass = static_cast<double>(s.n_expect) / plan.passes;
     const double false_est =
         plan.passes * per_pass * per_pass / 2.0 / std::ldexp(1.0, static_cast<int>(keep + plan.b1bits + plan.b2bits));
-    j->compact = c->compact && (1u << lg) == sl && c->fp_mask == (1ull << kFpBits) - 1 && !c->join_sort &&
-                 f2 >= 24 && (c->compact_fp_bits || false_est <= kCompactFalseMax);
+    // Batched calls keep 12-byte entries unless asked (mode 2): their words need
+    // each entry's query table row, which measured slower than the bytes saved.
+    const bool mode = c->compact == 2 || (c->compact == 1 && !batch);
+    j->compact = mode && (1u << lg) == sl && c->fp_mask == (1ull << kFpBits) - 1 && !c->join_sort && f2 >= 24 &&
+                 (c->compact_fp_bits || false_est <= kCompactFalseMax);
     if (j->compact) {
       j->low_mask = (1ull << keep) - 1;
       const uint32_t b2shift = plan.b2bits ? kFpBits - plan.b2bits : kFpBits;
@@ -936,6 +954,7 @@ int enqueue_verify(bx_ctx* c, const Job& j, uint32_t grid, hipStream_t st) {
   V.n_cand = static_cast<const uint32_t*>(c->flags.p) + kFlagCand;
   V.cand_cap = kCandCap;
   V.primes = c->d_primes;
+  V.pinv = c->d_pinv;
   V.n_primes = static_cast<uint32_t>(c->primes.size());
   V.queries = static_cast<const Query*>(c->queries.p);
   V.batch = j.batch;
@@ -1650,6 +1669,7 @@ void bx_destroy(bx_ctx* c) {
                     &c->a2v[1], &c->a2hist, &c->a2offs, &c->a2tot})
     free_buf(*b);
   if (c->d_primes) (void)hipFree(c->d_primes);
+  if (c->d_pinv) (void)hipFree(c->d_pinv);
   if (c->d_pp) (void)hipFree(c->d_pp);
   for (DenseTab* d : c->d_dense)
     if (d) (void)hipFree(d);
@@ -1716,7 +1736,8 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
   } else if (n == "submit_wait") {
     c->submit_wait = v != 0;
   } else if (n == "compact") {
-    c->compact = v != 0;
+    if (v < 0 || v > 2) return fail(BX_EINVAL, "compact must be 0, 1 or 2");
+    c->compact = static_cast<int>(v);
   } else if (n == "compact_fp_bits") {
     if (v != 0 && (v < 12 || v > 40)) return fail(BX_EINVAL, "compact_fp_bits must be 0 or in [12, 40]");
     c->compact_fp_bits = static_cast<uint32_t>(v);

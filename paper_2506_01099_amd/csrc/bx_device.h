@@ -34,6 +34,12 @@ struct PrimePow {
   uint32_t pinv;
 };
 
+// Divisibility by an odd prime without division: p^-1 mod 2^64 and
+// floor((2^64 - 1) / p) (zero for p = 2, which is tested by its low bit).
+struct PrimeInv {
+  uint64_t inv, lim;
+};
+
 struct Query {
   uint64_t a, b;  // x in [a, b); radicals over [a, b]
 };

@@ -1060,6 +1060,7 @@ struct VerifyParams {
   const uint32_t* n_cand;  // candidate count, read on the device (graph replays)
   uint32_t cand_cap;
   const uint32_t* primes;  // all primes <= sqrt(hi_max), ascending
+  const PrimeInv* pinv;    // their inverses for the divisibility tests
   uint32_t n_primes;
   const Query* queries;
   int batch;
@@ -1097,15 +1098,26 @@ __global__ __launch_bounds__(BLOCK) void k_verify(VerifyParams P) {
     for (uint32_t i = tid; i < P.n_primes; i += BLOCK) {
       const uint64_t p = P.primes[i];
       if (p * p > vmax) break;
+      if (p == 2) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+          if (k < nv && 4 <= v[k] && (v[k] & 1) == 0) {
+            pr[k] *= 2;
+            sm[k] <<= __builtin_ctzll(v[k]);
+          }
+        }
+        continue;
+      }
+      // An odd p divides t iff t * p^-1 (mod 2^64) <= floor((2^64 - 1) / p),
+      // and that product is then t / p.
+      const PrimeInv pi = P.pinv[i];
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
-        if (k < nv && p * p <= v[k] && v[k] % p == 0) {
+        uint64_t t = v[k] * pi.inv;
+        if (k < nv && p * p <= v[k] && t <= pi.lim) {
           pr[k] *= p;
-          uint64_t t = v[k], pk = 1;
-          while (t % p == 0) {
-            t /= p;
-            pk *= p;
-          }
+          uint64_t pk = p;
+          for (uint64_t u = t * pi.inv; u <= pi.lim; u *= pi.inv) pk *= p;
           sm[k] *= pk;
         }
       }

@@ -502,16 +502,16 @@ def test_compact_words_match_oracle(ctx):
     from paper_2506_01099_amd.inputs import planted_queries
 
     a, b = planted_queries()
-    for compact, nbytes in ((1, 8), (0, 12)):
+    for compact, nbytes, nbytes_batch in ((2, 8, 8), (1, 8, 12), (0, 12, 12)):
         ctx.set_option("compact", compact)
         try:
             for N in (1 << 20, (1 << 24) + 77):
                 assert ctx.search(N) == oracle.search(N), (compact, N)
                 assert ctx.stats()["l2_entry_bytes"] == nbytes
             got = ctx.search_batch(a, b)
-            assert ctx.stats()["l2_entry_bytes"] == nbytes
+            assert ctx.stats()["l2_entry_bytes"] == nbytes_batch
         finally:
-            ctx.set_option("compact", 0)
+            ctx.set_option("compact", 1)
         for i in range(a.size):
             assert got[i] == oracle.search_range(int(a[i]), int(b[i]))
 
@@ -522,14 +522,14 @@ def test_compact_candidates_exact_2_24(ctx, keep):
     fingerprint bits in a word, different sets meet, and every pair of equal (bucket,
     partition, kept bits) must become a candidate."""
     N = 1 << 24
-    ctx.set_option("compact", 1)
+    ctx.set_option("compact", 2)
     ctx.set_option("compact_fp_bits", keep)
     try:
         got = ctx.search(N)
         st = ctx.stats()
     finally:
         ctx.set_option("compact_fp_bits", 0)
-        ctx.set_option("compact", 0)
+        ctx.set_option("compact", 1)
     assert got == oracle.search(N)
     assert st["l2_entry_bytes"] == 8 and st["retries"] == 0
     keys, n_kept = join_model.compact_keys(oracle.radicals(1, N + 2), 1, N + 1, 0, st["b1_bits"], st["b2_bits"], keep)
@@ -543,14 +543,14 @@ def test_compact_candidates_exact_2_24(ctx, keep):
 def test_compact_candidates_exact_2_28(ctx, rad_2_28):
     """The same at 2^28 (several first-level buckets), from the library's radicals."""
     N, keep = 1 << 28, 18
-    ctx.set_option("compact", 1)
+    ctx.set_option("compact", 2)
     ctx.set_option("compact_fp_bits", keep)
     try:
         got = ctx.search(N)
         st = ctx.stats()
     finally:
         ctx.set_option("compact_fp_bits", 0)
-        ctx.set_option("compact", 0)
+        ctx.set_option("compact", 1)
     assert got == theorem1_pairs(N)
     assert st["l2_entry_bytes"] == 8 and st["b1_bits"] >= 1
     keys, n_kept = join_model.compact_keys(rad_2_28, 1, N + 1, 0, st["b1_bits"], st["b2_bits"], keep)
@@ -565,7 +565,7 @@ def test_compact_candidates_exact_batched(ctx):
     not hold the query) and the verification drops them."""
     qs = [(1, 1 << 22), (1 << 22, 3 << 21), (5 << 30, (5 << 30) + (1 << 22))]
     keep = 14
-    ctx.set_option("compact", 1)
+    ctx.set_option("compact", 2)
     ctx.set_option("compact_fp_bits", keep)
     try:
         got = ctx.search_batch(np.array([q[0] for q in qs], dtype=np.uint64),
@@ -573,7 +573,7 @@ def test_compact_candidates_exact_batched(ctx):
         st = ctx.stats()
     finally:
         ctx.set_option("compact_fp_bits", 0)
-        ctx.set_option("compact", 0)
+        ctx.set_option("compact", 1)
     allkeys = []
     for i, (a, b) in enumerate(qs):
         assert got[i] == oracle.search_range(a, b)
