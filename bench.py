@@ -274,8 +274,8 @@ def main():
         parse_counters(*args.parse_counters)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described "
-              "in DESIGN.md and is not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path (passes or range "
+              "shares per GPU, one all-to-all of first-level buckets) is a design, not built", file=sys.stderr)
         sys.exit(2)
     import torch
 
