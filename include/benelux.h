@@ -89,8 +89,10 @@ int bx_set_stream(bx_ctx* ctx, void* hip_stream);
 int bx_radical_segment(bx_ctx* ctx, uint64_t lo, uint64_t hi, uint64_t* out);
 
 /* Same, writing into caller-owned device memory dev_out[hi - lo] on the HIP
- * stream `hip_stream` (NULL = the context's stream).  Returns once the kernels
- * are queued; the caller synchronises the stream. */
+ * stream `hip_stream`, which is the caller's: NULL is HIP's default (null)
+ * stream, as in HIP's own calls (and PyTorch's default stream), not the
+ * context's stream.  The kernels are ordered after the context's earlier work.
+ * Returns once they are queued; the caller synchronises the stream. */
 int bx_radical_segment_dev(bx_ctx* ctx, uint64_t lo, uint64_t hi, uint64_t* dev_out, void* hip_stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
@@ -210,7 +212,9 @@ typedef struct {
   uint64_t joined;            /* entries the join kernels read (equals entries)   */
   uint64_t false_candidates;  /* candidates whose sets differ (dropped by verify) */
   uint32_t l2_entry_bytes;    /* bytes per second-level entry: 8 (compact words) or 12 */
-  uint32_t reserved;
+  uint32_t word_matches;      /* compact words whose kept bits met (each pair read back
+                                 from the first level; candidates are those of them
+                                 with equal whole fingerprints and queries)        */
 } bx_stats;
 int bx_get_stats(bx_ctx* ctx, bx_stats* out);
 
@@ -249,12 +253,13 @@ int bx_get_stats(bx_ctx* ctx, bx_stats* out);
  *   "submit_wait"  serving: 1 = bx_submit queues (default), 0 = bx_submit
  *                  refuses with BX_EBUSY what cannot be admitted at once
  *   "compact"      the second partition level stores 8-byte words (the
- *                  entry's segment, offset and low fingerprint bits; the
- *                  partition index stands for the top bits) instead of 12-byte
- *                  entries where the plan allows it: power-of-two segment,
- *                  full fingerprints, hash join, and at most 3e5 expected
- *                  random matches for the verification.  0 = never, 1 =
- *                  single-range calls (default), 2 = batched calls too
+ *                  entry's index among its first-level bucket's regions and
+ *                  the low fingerprint bits; the partition index stands for
+ *                  the top bits) instead of 12-byte entries where the plan
+ *                  allows it: full fingerprints, hash join, and at most 3e5
+ *                  expected random matches of the kept bits (the join reads
+ *                  both entries of a match back from the first level).
+ *                  0 = never, 1 = where the plan allows (default)
  *   "compact_fp_bits" for tests of the compact join: keep only this many low
  *                  fingerprint bits in a compact word (12 .. 40; 0 = all the
  *                  word holds), so that different sets meet

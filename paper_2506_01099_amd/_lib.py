@@ -48,7 +48,7 @@ class Stats(ctypes.Structure):
                 ("total_ms", ctypes.c_double), ("b1_bits", ctypes.c_uint32), ("b2_bits", ctypes.c_uint32),
                 ("seg_len", ctypes.c_uint32), ("tile", ctypes.c_uint32), ("graph_ms", ctypes.c_double),
                 ("joined", ctypes.c_uint64), ("false_candidates", ctypes.c_uint64),
-                ("l2_entry_bytes", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("l2_entry_bytes", ctypes.c_uint32), ("word_matches", ctypes.c_uint32)]
 
 
 _lib = None

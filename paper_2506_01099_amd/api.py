@@ -71,6 +71,7 @@ class Benelux:
             "total_ms": st.total_ms, "b1_bits": st.b1_bits, "b2_bits": st.b2_bits,
             "seg_len": st.seg_len, "tile": st.tile, "graph_ms": st.graph_ms,
             "joined": st.joined, "false_candidates": st.false_candidates, "l2_entry_bytes": st.l2_entry_bytes,
+            "word_matches": st.word_matches,
         }
 
     def autotune(self, a, b, reps=1, path=None):
@@ -97,7 +98,9 @@ class Benelux:
         return out[:n]
 
     def radical_segment_dev(self, lo, hi, out_tensor, stream=None):
-        """Write rad(x), x in [lo, hi), into a torch uint64/int64 CUDA tensor on `stream`."""
+        """Write rad(x), x in [lo, hi), into a torch uint64/int64 CUDA tensor on `stream`
+        (torch's current stream by default; its handle is 0 for the default stream, which
+        the library takes as HIP's null stream)."""
         import torch
 
         n = max(0, int(hi) - int(lo))

@@ -130,7 +130,7 @@ struct bx_ctx {
   uint32_t small_max = kSmallMaxLen;  // longest query of the small class (0: class off)
   int small_block = 1024;             // threads of a small-class workgroup
   int submit_wait = 1;                // 0: bx_submit refuses what cannot be admitted at once
-  int compact = 1;                    // 8-byte second-level words where the plan allows: 0 never, 1 single-range calls, 2 all
+  int compact = 1;                    // 8-byte second-level words where the plan allows (0 = never)
   uint32_t compact_fp_bits = 0;       // tests: fingerprint bits a compact word keeps (0 = all it can)
   int graph_batch = 1;      // batched calls run as one captured HIP graph
   bool capturing = false;   // no event records while a stream capture is open
@@ -672,18 +672,17 @@ struct Job {
   uint32_t sieve_grid = 0, B1 = 1, B2 = 1, G = 1, cpr = 1;
   uint64_t ngsub = 1, n_regions = 1, part_grid = 8;
   uint32_t gmask = 0;
-  // Compact second level (8-byte words): positions as (segment, offset), the
-  // low fingerprint bits above them.
+  // Compact second level (8-byte words): the entry's index among its bucket's
+  // first-level regions, the low fingerprint bits above it.
   bool compact = false;
-  uint32_t pos_bits = 0, seg_log2 = 0;
+  uint32_t idx_bits = 0;
   uint64_t low_mask = 0;
-  uint64_t fp_known = (1ull << kFpBits) - 1;  // fingerprint bits the candidates carry exactly
 };
 
-// Random matches a compact plan lets through to the verification (pairs of
-// different sets whose kept fingerprint bits, bucket and partition agree), at
-// most this many per call.
-constexpr double kCompactFalseMax = 3e5;
+// Random matches of kept word bits a compact plan expects (pairs of different
+// sets whose kept fingerprint bits, bucket and partition agree; the join reads
+// both entries of each back from the first level), at most this many per call.
+constexpr double kCompactMatchMax = 3e5;
 
 // Bytes of every workspace buffer a job needs.
 struct JobBufs {
@@ -716,32 +715,21 @@ int plan_job(bx_ctx* c, Segs& s, int batch, uint32_t kinds, Job* j, JobBufs* nb)
   if (j->part_grid > 0x7FFFFFFFull) return fail(BX_EINTERNAL, "partition grid too large");
   j->gmask = batch ? kGrpMask : 0u;
   nb->l1 = j->n_regions * plan.cap1 * sizeof(Entry);
-  // Compact words need a power-of-two segment, the full fingerprint (no test
-  // mask), the hash join, and enough kept bits that random matches stay few.
+  // Compact words need the full fingerprint (no test mask), the hash join, and
+  // enough kept bits that random matches stay few.
   {
-    const uint32_t sl = c->seg_len;
-    uint32_t lg = 0;
-    while ((1u << lg) < sl) ++lg;
-    uint32_t sb = 1;
-    while ((1ull << sb) < std::max<uint64_t>(2, s.n_segs)) ++sb;
-    j->seg_log2 = lg;
-    j->pos_bits = sb + lg;
-    const uint32_t f2 = 64 - std::min<uint32_t>(64, j->pos_bits);
+    const uint64_t per_bucket = static_cast<uint64_t>(j->sieve_grid) * plan.cap1;  // first-level slots of a bucket
+    uint32_t ib = 1;
+    while (ib < 64 && (1ull << ib) < per_bucket) ++ib;
+    j->idx_bits = ib;
+    const uint32_t f2 = std::min<uint32_t>(kFpBits, 64 - ib);
     const uint32_t keep = c->compact_fp_bits ? std::min(f2, c->compact_fp_bits) : f2;
     const double per_pass = static_cast<double>(s.n_expect) / plan.passes;
-    const double false_est =
+    const double match_est =
         plan.passes * per_pass * per_pass / 2.0 / std::ldexp(1.0, static_cast<int>(keep + plan.b1bits + plan.b2bits));
-    // Batched calls keep 12-byte entries unless asked (mode 2): their words need
-    // each entry's query table row, which measured slower than the bytes saved.
-    const bool mode = c->compact == 2 || (c->compact == 1 && !batch);
-    j->compact = mode && (1u << lg) == sl && c->fp_mask == (1ull << kFpBits) - 1 && !c->join_sort && f2 >= 24 &&
-                 (c->compact_fp_bits || false_est <= kCompactFalseMax);
-    if (j->compact) {
-      j->low_mask = (1ull << keep) - 1;
-      const uint32_t b2shift = plan.b2bits ? kFpBits - plan.b2bits : kFpBits;
-      const uint64_t part = b2shift < kFpBits ? (((1ull << plan.b2bits) - 1) << b2shift) : 0ull;
-      j->fp_known = (part | j->low_mask) & ((1ull << kFpBits) - 1);
-    }
+    j->compact = c->compact && c->fp_mask == (1ull << kFpBits) - 1 && !c->join_sort && f2 >= 24 &&
+                 (c->compact_fp_bits || match_est <= kCompactMatchMax);
+    if (j->compact) j->low_mask = (1ull << keep) - 1;
   }
   nb->l2 = j->ngsub * plan.cap2 * (j->compact ? sizeof(uint64_t) : sizeof(Entry));
   nb->cnt1 = j->n_regions * 4ull;
@@ -847,11 +835,7 @@ int enqueue_pass(bx_ctx* c, const Job& j, uint64_t ph_lo, uint64_t ph_hi, hipStr
     Q.gmask = j.gmask;
     Q.flags = d_flags;
     Q.l2c = static_cast<uint64_t*>(c->l2.p);
-    Q.batch = j.batch;
-    Q.queries = static_cast<const Query*>(c->queries.p);
-    Q.seg_prefix = static_cast<const uint64_t*>(c->segpref.p);
-    Q.seg_log2 = j.seg_log2;
-    Q.pos_bits = j.pos_bits;
+    Q.idx_bits = j.idx_bits;
     Q.low_mask = j.low_mask;
     {
       LaunchTimer t(c, K_PART, st);
@@ -875,13 +859,11 @@ int enqueue_pass(bx_ctx* c, const Job& j, uint64_t ph_lo, uint64_t ph_hi, hipStr
     J.flags = d_flags;
     J.joined = static_cast<unsigned long long*>(c->acc.p) + kAccJoined;
     J.l2c = static_cast<const uint64_t*>(c->l2.p);
-    J.pos_bits = j.pos_bits;
-    J.seg_log2 = j.seg_log2;
-    J.seg_prefix = static_cast<const uint64_t*>(c->segpref.p);
-    J.queries = static_cast<const Query*>(c->queries.p);
-    J.n_queries = static_cast<uint32_t>(j.s->q.size());
-    J.batch = j.batch;
-    J.b2shift = plan.b2bits ? kFpBits - plan.b2bits : kFpBits;
+    J.idx_bits = j.idx_bits;
+    J.l1 = static_cast<const Entry*>(c->l1.p);
+    J.cap1 = plan.cap1;
+    J.W = j.sieve_grid;
+    J.first = first;
     J.b2mask = j.B2 - 1;
     {
       LaunchTimer t(c, K_JOIN, st);
@@ -961,7 +943,6 @@ int enqueue_verify(bx_ctx* c, const Job& j, uint32_t grid, hipStream_t st) {
   V.kinds = j.kinds;
   V.third_off = c->third_off;
   V.fp_mask = c->fp_mask;
-  V.fp_known = j.fp_known;
   V.out = static_cast<OutPair*>(c->out.p);
   V.out_cap = kCandCap;
   V.flags = static_cast<uint32_t*>(c->flags.p);
@@ -990,6 +971,7 @@ int collect_pairs(bx_ctx* c, const uint32_t* fl, const unsigned long long* acc, 
     return fail(BX_EINTERNAL, std::to_string(fl[kFlagVerifyFail]) + " candidate pairs failed exact verification");
   c->stats.candidates = fl[kFlagCand];
   c->stats.false_candidates = fl[kFlagFalseCand];
+  c->stats.word_matches = fl[kFlagWordMatch];
   const uint32_t n_out = std::min(fl[kFlagOut], kCandCap);
   c->stats.pairs = n_out;
   result->resize(n_out);
@@ -1073,7 +1055,7 @@ int run_passes_graph(bx_ctx* c, Job& j, hipStream_t st, std::vector<OutPair>* re
                 j.G, static_cast<unsigned long long>(j.s->n_segs), static_cast<uint32_t>(j.s->q.size()), j.batch,
                 j.kinds, c->third_off, c->tile, c->seg_len, c->prune, c->join_sort,
                 static_cast<unsigned long long>(c->fp_mask), c->small_max, c->small_block, j.s->small.size(),
-                static_cast<int>(j.compact), j.pos_bits, static_cast<unsigned long long>(j.low_mask), c->l1.p,
+                static_cast<int>(j.compact), j.idx_bits, static_cast<unsigned long long>(j.low_mask), c->l1.p,
                 c->l2.p, c->spill.p, c->cnt1.p, c->cnt2.p, c->cand.p, c->out.p, c->flags.p, c->acc.p, c->queries.p,
                 c->segpref.p, c->smallq.p, static_cast<void*>(c->d_pp), static_cast<void*>(c->d_primes));
   if (!c->graph_exec || c->graph_key != key) {
@@ -1736,7 +1718,7 @@ int bx_set_option(bx_ctx* c, const char* name, int64_t v) {
   } else if (n == "submit_wait") {
     c->submit_wait = v != 0;
   } else if (n == "compact") {
-    if (v < 0 || v > 2) return fail(BX_EINVAL, "compact must be 0, 1 or 2");
+    if (v < 0 || v > 1) return fail(BX_EINVAL, "compact must be 0 or 1");
     c->compact = static_cast<int>(v);
   } else if (n == "compact_fp_bits") {
     if (v != 0 && (v < 12 || v > 40)) return fail(BX_EINVAL, "compact_fp_bits must be 0 or in [12, 40]");
@@ -1799,7 +1781,7 @@ int bx_radical_segment_dev(bx_ctx* c, uint64_t lo, uint64_t hi, uint64_t* dev_ou
   if (rc != BX_OK) return rc;
   if (hi == lo) return BX_OK;
   BX_HIP(hipSetDevice(c->device));
-  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  hipStream_t st = static_cast<hipStream_t>(stream);  // NULL: the default stream
   if ((rc = order_after_last(c, st)) != BX_OK) return rc;
   // The query tables are uploaded on `st`; the caller synchronises it.
   rc = radicals_into(c, lo, hi, dev_out, st);
@@ -1836,7 +1818,7 @@ int bx_radical_segment_dev_noalloc(bx_ctx* c, uint64_t lo, uint64_t hi, uint64_t
   BX_HIP(hipSetDevice(c->device));
   NaDevice* na = static_cast<NaDevice*>(c->na);
   std::lock_guard<std::mutex> lk_na(na->mu);
-  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  hipStream_t st = static_cast<hipStream_t>(stream);  // NULL: the default stream
   if ((rc = order_after_last(c, st)) != BX_OK) return rc;
   uint32_t* flags = reinterpret_cast<uint32_t*>(na->ptr);
   Query* q = reinterpret_cast<Query*>(na->ptr + kNaQueryOff);

@@ -76,7 +76,8 @@ enum : int {
   kFlagVerifyFail = 4,
   kFlagSpillOverflow = 5,
   kFlagFalseCand = 6,  // equal fingerprints of different sets (dropped)
-  kFlagCount = 7
+  kFlagWordMatch = 7,  // compact words with equal kept bits (each re-read from the first level)
+  kFlagCount = 8
 };
 
 // 64-bit per-call counters (acc[]): entries written by the sieve, entries read

@@ -604,29 +604,17 @@ struct PartParams {
   uint64_t fp_mask;          // fingerprint bits kept (all 53 but in tests of the verification)
   uint32_t gmask;
   uint32_t* flags;
-  // Compact second level: one 64-bit word per entry, fp_low << pos_bits |
-  // s << seg_log2 | off, with s the global segment of x and off its offset in
-  // that segment (the top of the fingerprint is the partition's own index).
+  // Compact second level: one 64-bit word per entry, fp_low << idx_bits | i,
+  // with i = w * cap1 + k the entry's index among its first-level bucket's
+  // regions (entry k of region (b, w)), which stay intact until the group is
+  // joined.  The top of the fingerprint is the partition's own index.
   uint64_t* l2c;
-  int batch;
-  const Query* queries;
-  const uint64_t* seg_prefix;
-  uint32_t seg_log2, pos_bits;
+  uint32_t idx_bits;
   uint64_t low_mask;  // fingerprint bits a compact word keeps
 };
 
-__device__ __forceinline__ uint64_t compact_word(const PartParams& P, const Entry& e) {
-  const uint64_t pos = entry_pos43(e);
-  uint64_t rel, s0;
-  if (P.batch) {
-    rel = pos & ((1ull << kGrpShift) - 1);
-    s0 = P.seg_prefix[(pos >> kGrpShift) & kGrpMask];
-  } else {
-    rel = pos - P.queries[0].a;
-    s0 = 0;
-  }
-  const uint64_t seg = s0 + (rel >> P.seg_log2), off = rel & ((1ull << P.seg_log2) - 1);
-  return ((entry_fp(e) & P.low_mask) << P.pos_bits) | (seg << P.seg_log2) | off;
+__device__ __forceinline__ uint64_t compact_word(const PartParams& P, const Entry& e, uint64_t idx) {
+  return ((entry_fp(e) & P.low_mask) << P.idx_bits) | idx;
 }
 
 // Second scatter of one group of first-level buckets into the group buffer.
@@ -664,7 +652,7 @@ __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
   // The partition of an entry is the top of its fingerprint.
   auto bucket_of = [&](uint32_t i) -> uint32_t { return sbk[i]; };
   // Chunk ci of the bucket: entries [s0, s0 + n) of region ci / cpr.
-  auto chunk = [&](uint64_t ci, const Entry** src) -> uint32_t {
+  auto chunk = [&](uint64_t ci, const Entry** src) -> uint32_t {  // ci < n_chunks
     const uint64_t region = static_cast<uint64_t>(b1) * P.W + ci / cpr;
     const uint64_t n1 = min(static_cast<uint64_t>(P.cnt1[region]), P.cap1);
     const uint64_t s0 = (ci % cpr) * static_cast<uint64_t>(kPartChunk);
@@ -680,6 +668,8 @@ __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
     if (i < n) e[q] = src[i];
   }
   for (uint64_t ci = c_begin; ci < c_end; ++ci) {
+    // Index of the chunk's first entry among the bucket's regions (compact words).
+    const uint64_t ibase = COMPACT ? (ci / cpr) * P.cap1 + (ci % cpr) * static_cast<uint64_t>(kPartChunk) : 0ull;
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       const uint32_t i = tid + q * BLOCK;
@@ -690,7 +680,7 @@ __global__ __launch_bounds__(BLOCK) void k_partition(PartParams P) {
           x = make_entry(pos43, entry_fp(x) & P.fp_mask);
         }
         if constexpr (COMPACT)
-          ent[i] = compact_word(P, x);
+          ent[i] = compact_word(P, x, ibase + i);
         else
           ent[i] = x;
         sbk[i] = static_cast<uint16_t>(static_cast<uint32_t>(entry_fp(e[q]) >> P.b2shift) & P.b2mask);
@@ -733,33 +723,20 @@ struct JoinParams {
   uint32_t cand_cap;
   uint32_t* flags;
   unsigned long long* joined;  // entries read, summed over partitions (64-bit: 2^36 searches pass 2^32)
-  // Compact second level (k_join_c): the words and what decodes them.
+  // Compact second level (k_join_c): the words and the first level they index.
   const uint64_t* l2c;
-  uint32_t pos_bits, seg_log2;
-  const uint64_t* seg_prefix;
-  const Query* queries;
-  uint32_t n_queries;
-  int batch;
-  uint32_t b2shift, b2mask;  // the partition index is the top of the fingerprint
+  uint32_t idx_bits;
+  const Entry* l1;
+  uint64_t cap1;
+  uint32_t W, first;  // regions per bucket; first first-level bucket of the group
+  uint32_t b2mask;    // sub-bucket sbk is partition sbk & b2mask of bucket first + sbk / (b2mask + 1)
 };
 
-// The 12-byte entry of a compact word: x from its segment and offset, and the
-// fingerprint bits known (the partition's index on top, the kept low bits).
+// The 12-byte entry a compact word of sub-bucket sbk stands for, read back
+// from its first-level region.
 __device__ __forceinline__ Entry compact_entry(const JoinParams& P, uint64_t w, uint64_t sbk) {
-  const uint64_t off = w & ((1ull << P.seg_log2) - 1);
-  const uint64_t seg = (w & ((1ull << P.pos_bits) - 1)) >> P.seg_log2;
-  uint32_t lo = 0, hi = P.n_queries;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (P.seg_prefix[mid] <= seg)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  const uint64_t rel = ((seg - P.seg_prefix[lo]) << P.seg_log2) | off;
-  const uint64_t pos43 = P.batch ? (rel | (static_cast<uint64_t>(lo) << kGrpShift)) : P.queries[0].a + rel;
-  const uint64_t part = P.b2shift < kFpBits ? ((sbk & P.b2mask) << P.b2shift) : 0ull;
-  return make_entry(pos43, part | (w >> P.pos_bits));
+  const uint64_t b1 = P.first + sbk / (static_cast<uint64_t>(P.b2mask) + 1);
+  return P.l1[b1 * P.W * P.cap1 + (w & ((1ull << P.idx_bits) - 1))];
 }
 
 __device__ __forceinline__ void emit_cand(const JoinParams& P, const Entry& a, const Entry& b) {
@@ -877,9 +854,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
 }
 
 // k_join over compact words: the same inserts and probes, on the kept low
-// fingerprint bits (the partition fixes the top ones); a match is decoded into
-// 12-byte entries for the verification, which also drops matches of different
-// queries.
+// fingerprint bits (the partition fixes the top ones).  Both entries of a
+// match are read back from the first level and become a candidate when their
+// whole fingerprints and queries agree, as in k_join.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void k_join_c(JoinParams P) {
   constexpr int EPT = kJoinCap / BLOCK;
@@ -898,15 +875,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
   }
   if (n < 2) return;
   const uint64_t* src = P.l2c + sbk * P.cap2;
-  const uint32_t pb = P.pos_bits;
+  const uint32_t pb = P.idx_bits;
   auto emit = [&](uint64_t a, uint64_t b) {
-    const uint32_t k = atomicAdd(&P.flags[kFlagCand], 1u);
-    if (k < P.cand_cap) {
-      Cand c;
-      c.a = compact_entry(P, a, sbk);
-      c.b = compact_entry(P, b, sbk);
-      P.cand[k] = c;
-    }
+    atomicAdd(&P.flags[kFlagWordMatch], 1u);
+    const Entry ea = compact_entry(P, a, sbk), eb = compact_entry(P, b, sbk);
+    if (entry_fp(ea) == entry_fp(eb) && entry_grp(ea, P.gmask) == entry_grp(eb, P.gmask)) emit_cand(P, ea, eb);
   };
   for (uint32_t i0 = 0; i0 < n; i0 += kJoinCap) {
     const uint32_t m = min(static_cast<uint32_t>(kJoinCap), n - i0);
@@ -1067,7 +1040,6 @@ struct VerifyParams {
   uint32_t kinds;
   uint32_t third_off;  // the third condition compares rad(m + third_off), rad(n + third_off) (2 in use)
   uint64_t fp_mask;
-  uint64_t fp_known;  // fingerprint bits the candidates carry exactly (all but after a compact join)
   OutPair* out;
   uint32_t out_cap;
   uint32_t* flags;
@@ -1151,7 +1123,7 @@ __global__ __launch_bounds__(BLOCK) void k_verify(VerifyParams P) {
                         entry_grp(cd.b, P.batch ? kGrpMask : 0u) == qa_idx;
       if (!same) {
         atomicAdd(&P.flags[kFlagFalseCand], 1u);  // equal fingerprints, different sets (or queries)
-      } else if ((((key64(lo_m, hi_m, P.batch ? qa_idx : 0u) >> 11) & P.fp_mask) ^ entry_fp(cd.a)) & P.fp_known) {
+      } else if (((key64(lo_m, hi_m, P.batch ? qa_idx : 0u) >> 11) & P.fp_mask) != entry_fp(cd.a)) {
         atomicAdd(&P.flags[kFlagVerifyFail], 1u);  // the entry does not hold this set's fingerprint
       } else {
         // Kind 1 iff rad(m) = rad(n) (Algorithm 2); the third-condition bit

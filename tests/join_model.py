@@ -103,8 +103,8 @@ def compact_keys(rad, a, b, grp, b1_bits, b2_bits, keep_bits):
     """For the query [a, b), the group of every kept entry under the compact second
     level (one pass): entries meet when their first-level bucket (low b1_bits of the
     key hash), their partition (top b2_bits of the 53-bit fingerprint) and the low
-    keep_bits of the fingerprint agree -- the query itself is not compared (the
-    verification drops matches across queries)."""
+    keep_bits of the fingerprint agree -- the query itself is not compared (the join
+    reads such matches back from the first level and drops those across queries)."""
     n = b - a
     x = np.arange(a, b, dtype=np.int64)
     r = rad.astype(np.int64)

@@ -497,12 +497,12 @@ def test_join_candidates_exact_batched(ctx):
 
 
 def test_compact_words_match_oracle(ctx):
-    """The second partition level as 8-byte words (segment, offset, low fingerprint
+    """The second partition level as 8-byte words (first-level index, low fingerprint
     bits) and as 12-byte entries give the oracle's lists."""
     from paper_2506_01099_amd.inputs import planted_queries
 
     a, b = planted_queries()
-    for compact, nbytes, nbytes_batch in ((2, 8, 8), (1, 8, 12), (0, 12, 12)):
+    for compact, nbytes, nbytes_batch in ((1, 8, 8), (0, 12, 12)):
         ctx.set_option("compact", compact)
         try:
             for N in (1 << 20, (1 << 24) + 77):
@@ -520,9 +520,10 @@ def test_compact_words_match_oracle(ctx):
 def test_compact_candidates_exact_2_24(ctx, keep):
     """Join completeness on compact words, counted exactly: with only `keep` low
     fingerprint bits in a word, different sets meet, and every pair of equal (bucket,
-    partition, kept bits) must become a candidate."""
+    partition, kept bits) must be found and read back; only equal whole fingerprints
+    become candidates."""
     N = 1 << 24
-    ctx.set_option("compact", 2)
+    ctx.set_option("compact", 1)
     ctx.set_option("compact_fp_bits", keep)
     try:
         got = ctx.search(N)
@@ -536,14 +537,14 @@ def test_compact_candidates_exact_2_24(ctx, keep):
     want = join_model.candidates(keys)
     assert st["entries"] == st["joined"] == n_kept
     assert 10**3 < want < 10**6
-    assert st["candidates"] == want
-    assert st["candidates"] == st["pairs"] + st["false_candidates"]
+    assert st["word_matches"] == want
+    assert st["candidates"] == st["pairs"] and st["false_candidates"] == 0
 
 
 def test_compact_candidates_exact_2_28(ctx, rad_2_28):
     """The same at 2^28 (several first-level buckets), from the library's radicals."""
     N, keep = 1 << 28, 18
-    ctx.set_option("compact", 2)
+    ctx.set_option("compact", 1)
     ctx.set_option("compact_fp_bits", keep)
     try:
         got = ctx.search(N)
@@ -557,15 +558,16 @@ def test_compact_candidates_exact_2_28(ctx, rad_2_28):
     want = join_model.candidates(keys)
     assert st["entries"] == st["joined"] == n_kept
     assert 10**3 < want < 10**6
-    assert st["candidates"] == want
+    assert st["word_matches"] == want
+    assert st["candidates"] == st["pairs"] and st["false_candidates"] == 0
 
 
 def test_compact_candidates_exact_batched(ctx):
-    """Batched compact words: matches across queries are candidates too (the words do
-    not hold the query) and the verification drops them."""
+    """Batched compact words: the words do not hold the query, so kept bits also meet
+    across queries; the join reads such matches back and drops them."""
     qs = [(1, 1 << 22), (1 << 22, 3 << 21), (5 << 30, (5 << 30) + (1 << 22))]
     keep = 14
-    ctx.set_option("compact", 2)
+    ctx.set_option("compact", 1)
     ctx.set_option("compact_fp_bits", keep)
     try:
         got = ctx.search_batch(np.array([q[0] for q in qs], dtype=np.uint64),
@@ -581,8 +583,8 @@ def test_compact_candidates_exact_batched(ctx):
         allkeys.append(keys)
     want = join_model.candidates(np.concatenate(allkeys))
     assert st["l2_entry_bytes"] == 8 and st["retries"] == 0 and want > 10**3
-    assert st["candidates"] == want
-    assert st["candidates"] == st["pairs"] + st["false_candidates"]
+    assert st["word_matches"] == want
+    assert st["candidates"] == st["pairs"] and st["false_candidates"] == 0
 
 
 @pytest.mark.parametrize("passes", [1, 2, 3, 5, 7, 16, 64])
