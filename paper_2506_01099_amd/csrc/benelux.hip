@@ -365,11 +365,12 @@ int make_plan(bx_ctx* c, uint64_t n_keys, uint64_t n_expect, uint64_t share, uin
     p.passes = P;
     // Fan-outs from the expected entries per pass; the regions from the bound.
     // The first level takes the fewest buckets whose second level still needs
-    // at most 2^10 partitions: every partition and join launch then moves as
+    // at most 2^11 partitions: every partition and join launch then moves as
     // much as it can (a small search runs one of each instead of one per
-    // group of a few thousand entries).
+    // group of a few thousand entries), and the sieve's flushes write longer
+    // runs per bucket.
     const double n_pass = std::max(1.0, std::ceil(static_cast<double>(std::min(n_expect, n_keys)) / P));
-    uint32_t b1 = std::min<uint32_t>(10, ceil_log2(n_pass * 1.03 / (7600.0 * 1024.0)));
+    uint32_t b1 = std::min<uint32_t>(10, ceil_log2(n_pass * 1.03 / (7600.0 * 2048.0)));
     if (c->force_b1 >= 0) b1 = static_cast<uint32_t>(c->force_b1);
     p.b1bits = b1;
     const double bucket = n_pass / std::ldexp(1.0, static_cast<int>(b1));
