@@ -453,7 +453,8 @@ def rad_2_28(ctx):
 
 @pytest.mark.parametrize("join,passes", [(0, 0), (0, 2), (1, 0)])
 def test_join_candidates_exact_2_28(ctx, rad_2_28, join, passes):
-    """The same exact candidate count at 2^28 (several first-level buckets), from the
+    """The same exact candidate count at 2^28 (four first-level buckets, forced: the plan
+    takes one bucket once a pass holds fewer than about 1.5e7 entries), from the
     library's radicals."""
     N, fp_bits = 1 << 28, 19
     rad = rad_2_28
@@ -461,6 +462,7 @@ def test_join_candidates_exact_2_28(ctx, rad_2_28, join, passes):
     ctx.set_option("fp_bits", fp_bits)
     ctx.set_option("passes", passes)
     ctx.set_option("join", join)
+    ctx.set_option("b1_bits", 2)
     try:
         got = ctx.search(N)
         st = ctx.stats()
@@ -468,8 +470,9 @@ def test_join_candidates_exact_2_28(ctx, rad_2_28, join, passes):
         ctx.set_option("fp_bits", 0)
         ctx.set_option("passes", 0)
         ctx.set_option("join", 0)
+        ctx.set_option("b1_bits", 0)
     assert got == theorem1_pairs(N)
-    assert st["retries"] == 0 and st["b1_bits"] >= 1
+    assert st["retries"] == 0 and st["b1_bits"] == 2
     want, n_kept = _expected_candidates(rad, 1, N + 1, 0, st, max(1, passes), fp_bits)
     assert st["entries"] == st["joined"] == n_kept
     assert 10**4 < want < 10**6
@@ -542,18 +545,20 @@ def test_compact_candidates_exact_2_24(ctx, keep):
 
 
 def test_compact_candidates_exact_2_28(ctx, rad_2_28):
-    """The same at 2^28 (several first-level buckets), from the library's radicals."""
+    """The same at 2^28 (four first-level buckets, forced), from the library's radicals."""
     N, keep = 1 << 28, 18
     ctx.set_option("compact", 1)
     ctx.set_option("compact_fp_bits", keep)
+    ctx.set_option("b1_bits", 2)
     try:
         got = ctx.search(N)
         st = ctx.stats()
     finally:
+        ctx.set_option("b1_bits", 0)
         ctx.set_option("compact_fp_bits", 0)
         ctx.set_option("compact", 1)
     assert got == theorem1_pairs(N)
-    assert st["l2_entry_bytes"] == 8 and st["b1_bits"] >= 1
+    assert st["l2_entry_bytes"] == 8 and st["b1_bits"] == 2
     keys, n_kept = join_model.compact_keys(rad_2_28, 1, N + 1, 0, st["b1_bits"], st["b2_bits"], keep)
     want = join_model.candidates(keys)
     assert st["entries"] == st["joined"] == n_kept
