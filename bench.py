@@ -186,13 +186,22 @@ def parse_counters(fetch_dir, write_dir):
 
 
 def load_traffic():
-    """Measured HBM bytes per launch, or None when the kernels changed since the counters were taken."""
+    """Measured HBM bytes per launch with the launches per search they were taken over, or
+    nothing when the kernels changed since the counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return {}
     t = json.load(open(TRAFFIC_FILE))
     if t.get("source_hash") != kernel_source_hash():
         return {}
-    return {k: v["fetch_bytes_per_launch"] + v["write_bytes_per_launch"] for k, v in t.get("kernels", {}).items()}
+    return {k: (v["fetch_bytes_per_launch"] + v["write_bytes_per_launch"], v["launches"])
+            for k, v in t.get("kernels", {}).items()}
+
+
+def traffic_of(traffic, kernel, launches, steps):
+    """Counter bytes per launch, only if the counters saw as many launches per search as this run
+    (a different plan moves different bytes per launch)."""
+    tr = traffic.get(kernel)
+    return tr[0] if tr and tr[1] * steps == launches else None
 
 
 def run_plain(bx, N, steps, warmup, warm_s=None):
@@ -239,7 +248,7 @@ def roofline_from(agg, n_ints_per_step, entries_per_step, steps, traffic):
         ints_per_launch = n_ints_per_step * steps / ln["sieve"]
         ach = SIEVE_OPS_PER_INT * ints_per_launch / (avg_ms * 1e-3) / 1e12
         out["sieve"] = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_INT_OPS / 1e12, "unit": "Tops/s",
-                        "frac": ach / (VALU_PEAK_INT_OPS / 1e12), "traffic": traffic.get("sieve"),
+                        "frac": ach / (VALU_PEAK_INT_OPS / 1e12), "traffic": traffic_of(traffic, "sieve", ln["sieve"], steps),
                         "avg_launch_ms": avg_ms, "integers_per_launch": ints_per_launch}
     # Partition: HBM-bound, a 12 B read and a 12 B (or 8 B compact) write per
     # entry (the entries the sieve wrote: the integers that pass the member test).
@@ -248,14 +257,16 @@ def roofline_from(agg, n_ints_per_step, entries_per_step, steps, traffic):
         b = (ENTRY_BYTES + l2) * entries_per_step * steps / ln["partition"]
         ach = b / (avg_ms * 1e-3) / 1e9
         out["partition"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": ach / HBM_PEAK_GBS, "traffic": traffic.get("partition"), "avg_launch_ms": avg_ms,
+                            "frac": ach / HBM_PEAK_GBS, "traffic": traffic_of(traffic, "partition", ln["partition"], steps),
+                            "avg_launch_ms": avg_ms,
                             "bytes_per_launch": b}
     if ln["join"]:
         avg_ms = ms["join"] / ln["join"]
         b = l2 * entries_per_step * steps / ln["join"]
         ach = b / (avg_ms * 1e-3) / 1e9
         out["join"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": ach / HBM_PEAK_GBS, "traffic": traffic.get("join"), "avg_launch_ms": avg_ms,
+                       "frac": ach / HBM_PEAK_GBS, "traffic": traffic_of(traffic, "join", ln["join"], steps),
+                       "avg_launch_ms": avg_ms,
                        "bytes_per_launch": b}
     # The join as a whole (second scatter + LDS join) against 24 B per key (the
     # sieve's 12 B entry read and its second-level copy written), whatever the

@@ -103,7 +103,11 @@ def test_counter_parsing_scales_by_the_calibration_copy(tmp_path, monkeypatch):
     # The file is tagged with the current kernel sources and is read back as bytes per launch.
     assert t["source_hash"] == bench.kernel_source_hash()
     traffic = bench.load_traffic()
-    assert traffic["join"] == pytest.approx(7.0 * 1024 * 2 + 0.5 * 1024)
+    assert traffic["join"][0] == pytest.approx(7.0 * 1024 * 2 + 0.5 * 1024) and traffic["join"][1] == 1
+    # Reported only for a run with as many launches per search as the counters saw.
+    assert bench.traffic_of(traffic, "partition", 6, 3) == pytest.approx(20.0 * 1024 * 2 + 30.0 * 1024)
+    assert bench.traffic_of(traffic, "partition", 4, 3) is None
+    assert bench.traffic_of(traffic, "verify", 1, 1) is None
 
 
 def test_stale_counters_are_not_reported(tmp_path, monkeypatch):
