@@ -14,6 +14,15 @@ FIRST, SECOND, BOTH, THIRD = 1, 2, 3, 4  # THIRD: also rad(m+2) = rad(n+2) (kind
 VALUE_LIMIT = 1 << 42
 
 
+def _split_by_offsets(flat, offs, q):
+    """Per-query slices of a flat pair list, offs holding the q + 1 running offsets (a
+    ctypes size_t array): one bulk conversion of the offsets instead of q * 2 ctypes reads."""
+    if not flat:
+        return [[] for _ in range(q)]
+    b = np.frombuffer(offs, dtype=np.uintp, count=q + 1).tolist()
+    return [flat[b[i]:b[i + 1]] for i in range(q)]
+
+
 def _pairs_from(ptr, count):
     lib = load()
     try:
@@ -137,8 +146,7 @@ class Benelux:
         P64 = ctypes.POINTER(ctypes.c_uint64)
         check(self._lib.bx_search_batch(self._h, a.ctypes.data_as(P64), b.ctypes.data_as(P64), q, int(kinds),
                                         ctypes.byref(p), offs))
-        flat = _pairs_from(p, offs[q])
-        return [flat[offs[i]:offs[i + 1]] for i in range(q)]
+        return _split_by_offsets(_pairs_from(p, offs[q]), offs, q)
 
 
 class Server:

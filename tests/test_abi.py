@@ -59,3 +59,20 @@ def test_create_without_gpu_reports_device_error():
     with pytest.raises(bx.BxError) as ei:
         bx.Benelux(device=0, hi_max=2**20)
     assert ei.value.code == _lib.BX_EDEVICE
+
+
+def test_batch_result_split_by_offsets():
+    """The binding's per-query split of a batched call's flat pair list (argument
+    marshalling only) against slicing with each offset read one by one."""
+    import ctypes
+
+    from paper_2506_01099_amd.api import _split_by_offsets
+
+    for counts in ([], [0], [0, 0, 0], [2, 0, 1, 0, 3], [0] * 4096):
+        q = len(counts)
+        offs = (ctypes.c_size_t * (q + 1))()
+        for i, c in enumerate(counts):
+            offs[i + 1] = offs[i] + c
+        flat = [(i, i + 1, 1) for i in range(offs[q])]
+        want = [flat[offs[i]:offs[i + 1]] for i in range(q)]
+        assert _split_by_offsets(flat, offs, q) == want
